@@ -1,0 +1,109 @@
+"""ctypes binding of libapic.so (the C ABI in include/apic_contact.h).
+
+Argument marshalling only: every step of the contact path runs in the HIP
+library.  Importing this module on a machine without the built library
+raises immediately; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapic.so")
+
+OK = 0
+E_INVALID = -1
+E_NOMEM = -2
+E_OUT_OF_GRID = -3
+E_DEVICE = -4
+E_BUDGET = -5
+E_KEY_OVERFLOW = -6
+E_BODY = -7
+
+FP64 = 0
+FP32_MIXED = 1
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("h", ctypes.c_double),
+                ("dims", ctypes.c_int32 * 3)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("P_before", ctypes.c_double * 3), ("P_after", ctypes.c_double * 3),
+                ("L_before", ctypes.c_double * 3), ("L_after", ctypes.c_double * 3),
+                ("E_before", ctypes.c_double), ("E_after", ctypes.c_double),
+                ("P_scale", ctypes.c_double), ("L_scale", ctypes.c_double),
+                ("n_particles", ctypes.c_int64), ("n_unconstrained", ctypes.c_int64),
+                ("grid_blocks", ctypes.c_int64)]
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("count", ctypes.c_int64), ("grid", Grid),
+                ("mu", ctypes.c_double), ("n_iter", ctypes.c_int32),
+                ("n_bodies", ctypes.c_int32)]
+
+
+# (name, restype, argtypes) of every exported entry point
+P = ctypes.c_void_p
+SIGNATURES = {
+    "apic_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t]),
+    "apic_destroy": (None, [P]),
+    "apic_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "apic_contact_step": (ctypes.c_int, [P, P, ctypes.POINTER(Grid), ctypes.c_int64, P, P, P, P,
+                                         P, ctypes.c_double, ctypes.c_int32, ctypes.c_int,
+                                         ctypes.POINTER(Report)]),
+    "apic_contact_step_batched": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
+                                                 ctypes.c_int64, P, P, P, P, P, ctypes.c_int,
+                                                 ctypes.POINTER(Report)]),
+    "apic_sort_keys": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
+                                      ctypes.c_int64, P, P, ctypes.c_int, P, P]),
+    "apic_scene_footprint": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]),
+}
+
+_lib = None
+
+
+class ApicError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = lib().apic_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def lib():
+    """Load libapic.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, where: str):
+    if rc != OK:
+        raise ApicError(rc, where)
+
+
+def make_grid(h: float, origin=(0.0, 0.0, 0.0), dims=(0, 0, 0)) -> Grid:
+    g = Grid()
+    g.origin[:] = [float(o) for o in origin]
+    g.h = float(h)
+    g.dims[:] = [int(d) for d in dims]
+    return g
+
+
+def report_dict(r: Report) -> dict:
+    return {"P_before": list(r.P_before), "P_after": list(r.P_after),
+            "L_before": list(r.L_before), "L_after": list(r.L_after),
+            "E_before": r.E_before, "E_after": r.E_after, "P_scale": r.P_scale,
+            "L_scale": r.L_scale, "n_particles": r.n_particles,
+            "n_unconstrained": r.n_unconstrained, "grid_blocks": r.grid_blocks}

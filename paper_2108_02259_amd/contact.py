@@ -1,0 +1,117 @@
+"""Python front end of the contact library: torch tensors in, C ABI calls out.
+
+Tensors are device tensors in the library's layout: x, v of shape (3, n),
+C of shape (9, n), m of shape (n,) -- float64 for the FP64 path, float32
+for the mixed path -- and body ids as an (n,) int16/uint16 tensor whose bits
+are the uint16 ids.  PyTorch supplies memory and the current stream; all
+arithmetic runs in libapic.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib, make_grid
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def precision_of(x: torch.Tensor) -> int:
+    if x.dtype == torch.float64:
+        return _lib.FP64
+    if x.dtype == torch.float32:
+        return _lib.FP32_MIXED
+    raise TypeError(f"unsupported dtype {x.dtype}")
+
+
+def _check_tensors(x, v, C, m, body):
+    n = x.shape[1]
+    dt = x.dtype
+    for name, t, shape in (("x", x, (3, n)), ("v", v, (3, n)), ("C", C, (9, n)), ("m", m, (n,))):
+        if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: expected contiguous {dt} cuda tensor of shape {shape}")
+    if tuple(body.shape) != (n,) or body.element_size() != 2 or not body.is_contiguous():
+        raise ValueError("body: expected contiguous 16-bit tensor of shape (n,)")
+    return n
+
+
+class Context:
+    """One library context (workspace arena) on a device."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self._h = ctypes.c_void_p()
+        check(lib().apic_create(ctypes.byref(self._h), int(device), int(budget_bytes)),
+              "apic_create")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().apic_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def contact_step(self, x, v, C, m, body, h, origin=(0.0, 0.0, 0.0), dims=(0, 0, 0),
+                     mu=0.0, n_iter=1, report=True):
+        """Overwrite v and C with the preferred generalized velocity S(v, C)."""
+        n = _check_tensors(x, v, C, m, body)
+        g = make_grid(h, origin, dims)
+        rep = _lib.Report()
+        rc = lib().apic_contact_step(self._h, _stream(), ctypes.byref(g), n, _ptr(x), _ptr(v),
+                                     _ptr(C), _ptr(m), _ptr(body), float(mu), int(n_iter),
+                                     precision_of(x), ctypes.byref(rep) if report else None)
+        check(rc, "apic_contact_step")
+        return _lib.report_dict(rep) if report else None
+
+    def contact_step_batched(self, scenes, x, v, C, m, body, report=True):
+        """scenes: list of dicts with offset, count, h, origin, dims, mu, n_iter, n_bodies."""
+        n = _check_tensors(x, v, C, m, body)
+        arr = (_lib.Scene * len(scenes))()
+        for i, s in enumerate(scenes):
+            arr[i].offset = int(s["offset"])
+            arr[i].count = int(s["count"])
+            arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
+            arr[i].mu = float(s["mu"])
+            arr[i].n_iter = int(s["n_iter"])
+            arr[i].n_bodies = int(s["n_bodies"])
+        reps = (_lib.Report * len(scenes))()
+        rc = lib().apic_contact_step_batched(self._h, _stream(), arr, len(scenes), n, _ptr(x),
+                                             _ptr(v), _ptr(C), _ptr(m), _ptr(body),
+                                             precision_of(x), reps if report else None)
+        check(rc, "apic_contact_step_batched")
+        return [_lib.report_dict(r) for r in reps] if report else None
+
+    def sort_keys(self, scenes, x, body):
+        """(sorted keys, permutation) as int64 cuda tensors."""
+        n = x.shape[1]
+        arr = (_lib.Scene * len(scenes))()
+        for i, s in enumerate(scenes):
+            arr[i].offset = int(s["offset"])
+            arr[i].count = int(s["count"])
+            arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
+            arr[i].mu = float(s.get("mu", 0.0))
+            arr[i].n_iter = int(s.get("n_iter", 0))
+            arr[i].n_bodies = int(s["n_bodies"])
+        keys = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+        rc = lib().apic_sort_keys(self._h, _stream(), arr, len(scenes), n, _ptr(x), _ptr(body),
+                                  precision_of(x), _ptr(keys), _ptr(perm))
+        check(rc, "apic_sort_keys")
+        mask = (1 << 32) - 1
+        return (keys[:n].to(torch.int64) & mask), (perm[:n].to(torch.int64) & mask)
+
+
+def footprint(n: int, blocks_hint: int = 0, precision: int = _lib.FP32_MIXED) -> int:
+    return int(lib().apic_scene_footprint(int(n), int(blocks_hint), int(precision)))

@@ -1,0 +1,137 @@
+// apic_internal.h -- internal types shared by the HIP translation units of the
+// contact library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apic_contact.h"
+
+namespace apic {
+
+// ---------------------------------------------------------------------------
+// Layout constants
+// ---------------------------------------------------------------------------
+// A "block" is 4x4x4 grid cells.  A particle in cell c (per axis) touches the
+// quadratic-spline nodes c-1 .. c+2 (Appendix B).  Node blocks are shifted by
+// one node: node block k holds nodes 4k-1 .. 4k+2, so every particle of cell
+// block B touches only node blocks B and B+1 per axis (8 node blocks).  The
+// LDS tile of a cell block is the 8x8x8 node cube of those 8 node blocks;
+// local node l = (cell in block) + stencil offset, 0 <= l < 7 per axis.
+constexpr int kBlock = 4;
+constexpr int kNodesPerBlock = 64;
+constexpr int kTileX = 8;               // tile row length
+constexpr int kTileY = 8;               // rows per slab
+constexpr int kTileZStride = 8 * 8 + 4; // padded slab stride (LDS banks)
+constexpr int kTileSize = 8 * kTileZStride;  // elements per component
+constexpr int kItem = 64;                // particles per work item (one wave)
+constexpr int kMaxKeyBlocks = 1 << 26;   // 26 block bits + 6 cell bits = 32
+
+// Error bits accumulated on the device.
+enum : int32_t {
+  kErrOutOfGrid = 1,
+  kErrKeyOverflow = 2,
+  kErrCapacity = 4,
+  kErrBody = 8,
+  kErrNonFinite = 16,
+};
+
+// ---------------------------------------------------------------------------
+// Tables (device memory)
+// ---------------------------------------------------------------------------
+struct SceneDev {
+  double origin[3];
+  double h;
+  double mu;
+  int64_t offset, count;
+  int32_t dims[3];
+  int32_t n_iter;
+  int32_t body_base;  // capacity index of this scene's body 0
+  int32_t n_bodies;   // body ids must be < n_bodies
+};
+
+// Accumulated with atomics while cells are computed.
+struct SceneAcc {
+  int32_t bmin[3], bmax[3];  // cell-block box
+  int32_t max_body;
+  int32_t pad;
+};
+
+struct BodyAcc {
+  int32_t bmin[3], bmax[3];
+};
+
+// Derived once per step from the boxes.
+struct SceneLay {
+  int64_t smap_off;      // offset of this scene's node-block map
+  int32_t smin[3];       // node-block map origin (= cell-block box min)
+  int32_t sext[3];       // node-block map extent (= box extent + 1)
+};
+
+struct BodyLay {
+  int64_t bmap_off;      // offset of this body's node-block map
+  int32_t bmin[3];       // cell-block box min
+  int32_t ext[3];        // cell-block box extent (0 if empty)
+  int32_t key_off;       // first key block of this body
+  int32_t scene;
+};
+
+// One segment = the particles of one (body, cell block).
+struct Segment {
+  int32_t start, count;
+  int32_t body;          // capacity body index
+  int32_t scene;
+  int32_t B[3];          // cell-block coordinates
+  int32_t sslot[8];      // shared-grid node-block slots, j = jx + 2 jy + 4 jz
+  int32_t bslot[8];      // body-grid node-block slots
+};
+
+struct Item {
+  int32_t seg, start, count, pad;
+};
+
+// Counters written by the device, read back by the host when it sizes
+// buffers, and checked for errors after a step.
+struct Counters {
+  int32_t err;
+  int32_t key_blocks;
+  int32_t n_seg;
+  int32_t n_items;
+  int32_t n_sblocks;     // active shared-grid node blocks
+  int32_t n_bblocks;     // active body-grid node blocks
+  int32_t pad0, pad1;
+  int64_t smap_total;
+  int64_t bmap_total;
+};
+
+// Per-scene FP64 reductions: P(3) L(3) E Pscale Lscale count uncon.
+constexpr int kRed = 11;
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tile_index(int lx, int ly, int lz) {
+  return lx + kTileX * ly + kTileZStride * lz;
+}
+
+// Node n (0..63, x fastest) of node block j (0..7) in the 8x8x8 tile.
+__device__ __forceinline__ int tile_index_block(int j, int n) {
+  int lx = 4 * (j & 1) + (n & 3);
+  int ly = 4 * ((j >> 1) & 1) + ((n >> 2) & 3);
+  int lz = 4 * (j >> 2) + (n >> 4);
+  return tile_index(lx, ly, lz);
+}
+
+__device__ __forceinline__ int floor_div4(int c) { return c >> 2; }  // arithmetic shift
+
+// Binary search: the scene whose [offset, offset+count) holds particle p.
+__device__ __forceinline__ int scene_of(const SceneDev *sc, int ns, int64_t p) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sc[mid].offset <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace apic

@@ -1,0 +1,102 @@
+// kernels.h -- host-side launchers of the library's HIP kernels.
+#pragma once
+
+#include "apic_internal.h"
+
+namespace apic {
+
+// ---- scan / fill (sort.hip) ------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+inline int64_t scan_partials_needed(int64_t n_cap) {
+  return (n_cap + kScanTile - 1) / kScanTile + 1;
+}
+
+// Exclusive prefix sum of in[0, n) into out (may alias in).  n is n_dev[0]
+// when n_dev is non-null (n_cap bounds it), else n_cap.  The total is written
+// to *total (int64).  mode 1 writes -1 where in[i] == 0 (slot maps).
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_t *n_dev,
+                    int64_t *total, int32_t *partial, int mode, hipStream_t st);
+
+void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, int64_t scale,
+              hipStream_t st);
+void fill_bytes_zero(void *p, int64_t bytes, hipStream_t st);
+void fill_zero_f(void *p, int64_t elems_cap, const int32_t *n_dev, int64_t per, int elem_bytes,
+                 hipStream_t st);
+
+// ---- radix sort (sort.hip) -------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// Stable LSD radix sort of (key, index) over the low `bits` key bits, 8 bits
+// per pass.  keys/vals ping-pong between the a and b buffers; the return value
+// is 0 if the result is in (ka, va), 1 if in (kb, vb).  Values start as the
+// identity permutation 0..n-1 (va need not be initialised).
+int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n, int bits,
+               uint32_t *hist, int32_t *partial, int64_t *total, hipStream_t st);
+
+// ---- layout (layout.hip) ---------------------------------------------------
+template <typename T>
+void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
+                  SceneAcc *sacc, BodyAcc *bacc, Counters *cnt, hipStream_t st);
+void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
+                        hipStream_t st);
+void launch_domains(const SceneDev *sc, int ns, const SceneAcc *sacc, const BodyAcc *bacc,
+                    SceneLay *slay, BodyLay *blay, Counters *cnt, hipStream_t st);
+template <typename T>
+void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
+                 const BodyLay *blay, uint32_t *keys, hipStream_t st);
+template <typename T>
+void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
+                   const T *m, const uint16_t *body, const SceneDev *sc, int ns,
+                   T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
+                   T *x_out, uint16_t *body_out, double *red, hipStream_t st);
+void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
+                     int64_t *tot, const int32_t *sbody, const BodyLay *blay,
+                     Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,
+                     int32_t *seg_tmp, Counters *cnt, hipStream_t st);
+void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
+                 int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
+                 int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,
+                 int64_t bblk_cap, hipStream_t st);
+
+// ---- transfers (transfer.hip) ---------------------------------------------
+struct GridPtrs {
+  void *mass;        // [sblk][64] T
+  void *buf[2];      // [sblk][3][64] T each
+  double *bmass;     // [bblk][64]
+};
+
+struct StepArgs {
+  const SceneDev *sc;
+  const Segment *seg;
+  const Item *items;
+  const Counters *cnt;
+  const uint32_t *keys;  // sorted
+  int64_t n;
+  int grid_wg;           // persistent workgroups
+};
+
+template <typename T>
+void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
+                 hipStream_t st);
+template <typename T>
+void launch_gridvel(const StepArgs &a, GridPtrs g, int cur, hipStream_t st);
+// One fused round k >= 1: G2P of buffer `cur`, the rule, P2G of the next
+// series field into buffer 1-cur.  Scenes whose n_iter == k-1 finish here.
+template <typename T>
+void launch_iter(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, T *nrm, T *Y,
+                 GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out, T *x_io,
+                 double dt, double *red, hipStream_t st);
+// Final G2P (k = max n_iter + 1): Vhat = Vbar + D for the remaining scenes.
+template <typename T>
+void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *Y,
+                  GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out, T *x_io,
+                  double dt, double *red, hipStream_t st);
+
+}  // namespace apic

@@ -1,0 +1,621 @@
+// layout.hip -- cell keys, the sorted particle layout, segments, work items and
+// the sparse node-block maps of the shared and per-body grids.
+//
+// Cells follow Appendix B: the base node of a particle is floor((x - o)/h),
+// computed in FP64 so that every precision path (and the CPU reference) agrees
+// bit for bit on the cell, hence on keys and order.
+#include <climits>
+
+#include "kernels.h"
+
+namespace apic {
+
+// ---------------------------------------------------------------------------
+// cells and boxes
+// ---------------------------------------------------------------------------
+struct CellInfo {
+  int32_t c[3];
+  double t[3];
+  bool ok;
+  int err;
+};
+
+template <typename T>
+__device__ __forceinline__ CellInfo cell_of(const T *x, int64_t n, int64_t p, const SceneDev &s) {
+  CellInfo ci;
+  ci.ok = true;
+  ci.err = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double xi = ((double)x[d * n + p] - s.origin[d]) / s.h;
+    double f = floor(xi);
+    if (!(f >= -1073741824.0 && f <= 1073741823.0)) {  // NaN fails too
+      ci.ok = false;
+      ci.err |= (xi != xi) ? kErrNonFinite : kErrOutOfGrid;
+      f = 0.0;
+    }
+    ci.c[d] = (int32_t)f;
+    ci.t[d] = xi - f;
+    if (s.dims[d] > 0 && (ci.c[d] < 1 || ci.c[d] > s.dims[d] - 3)) {
+      ci.ok = false;
+      ci.err |= kErrOutOfGrid;
+    }
+  }
+  return ci;
+}
+
+__device__ __forceinline__ void wave_minmax3(int32_t mn[3], int32_t mx[3]) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], o, 64));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], o, 64));
+    }
+}
+
+// Box update for the key `id` of each lane: one set of atomics per wave when
+// the wave is uniform in `id`, otherwise per lane.
+__device__ __forceinline__ void box_update(bool ok, int id, const int32_t B[3], int32_t *bmin,
+                                           int32_t *bmax, int stride) {
+  const int lane = threadIdx.x & 63;
+  uint64_t valid = __ballot(ok);
+  if (valid == 0) return;
+  int first = __ffsll((unsigned long long)valid) - 1;
+  int id0 = __shfl(id, first, 64);
+  bool uniform = __ballot(ok && id != id0) == 0;
+  if (uniform) {
+    int32_t mn[3], mx[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = ok ? B[d] : INT_MAX;
+      mx[d] = ok ? B[d] : INT_MIN;
+    }
+    wave_minmax3(mn, mx);
+    if (lane == first)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&bmin[(int64_t)id0 * stride + d], mn[d]);
+        atomicMax(&bmax[(int64_t)id0 * stride + d], mx[d]);
+      }
+  } else if (ok) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&bmin[(int64_t)id * stride + d], B[d]);
+      atomicMax(&bmax[(int64_t)id * stride + d], B[d]);
+    }
+  }
+}
+
+__global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) {
+    for (int d = 0; d < 3; ++d) {
+      sacc[i].bmin[d] = INT_MAX;
+      sacc[i].bmax[d] = INT_MIN;
+    }
+    sacc[i].max_body = -1;
+  }
+  if (i < nb_cap)
+    for (int d = 0; d < 3; ++d) {
+      bacc[i].bmin[d] = INT_MAX;
+      bacc[i].bmax[d] = INT_MIN;
+    }
+  if (i == 0) {
+    Counters z = {};
+    *cnt = z;
+  }
+}
+
+void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
+                        hipStream_t st) {
+  int64_t m = ns > nb_cap ? ns : nb_cap;
+  if (m < 1) m = 1;
+  k_layout_init<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(sacc, ns, bacc, nb_cap, cnt);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body, int64_t n,
+                                               const SceneDev *sc, int ns, SceneAcc *sacc,
+                                               BodyAcc *bacc, Counters *cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = p < n;
+  int s = 0, gb = 0, err = 0, b = 0;
+  int32_t B[3] = {0, 0, 0};
+  if (ok) {
+    s = scene_of(sc, ns, p);
+    const SceneDev sd = sc[s];
+    CellInfo ci = cell_of(x, n, p, sd);
+    err |= ci.err;
+    b = body[p];
+    if (b >= sd.n_bodies) {
+      err |= kErrBody;
+      ci.ok = false;
+    }
+    gb = sd.body_base + b;
+    ok = ci.ok;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) B[d] = floor_div4(ci.c[d]);
+  }
+  if (err) atomicOr(&cnt->err, err);
+  box_update(ok, gb, B, &bacc[0].bmin[0], &bacc[0].bmax[0], 6);
+  box_update(ok, s, B, &sacc[0].bmin[0], &sacc[0].bmax[0], 8);
+  // max body id per scene
+  uint64_t valid = __ballot(ok);
+  if (valid) {
+    int first = __ffsll((unsigned long long)valid) - 1;
+    int s0 = __shfl(s, first, 64);
+    bool uniform = __ballot(ok && s != s0) == 0;
+    int mb = ok ? b : -1;
+    if (uniform) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) mb = max(mb, __shfl_xor(mb, o, 64));
+      if ((int)(threadIdx.x & 63) == first) atomicMax(&sacc[s0].max_body, mb);
+    } else if (ok) {
+      atomicMax(&sacc[s].max_body, b);
+    }
+  }
+}
+
+template <typename T>
+void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
+                  SceneAcc *sacc, BodyAcc *bacc, Counters *cnt, hipStream_t st) {
+  if (n <= 0) return;
+  k_cells<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x, body, n, sc, ns, sacc, bacc, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// domains: body key offsets and node-block maps (one workgroup)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t block_excl_scan64(int64_t x, int64_t *lds, int64_t *total) {
+  // 1024 threads, simple two-level scan through LDS
+  const int tid = threadIdx.x;
+  lds[tid] = x;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t y = tid >= o ? lds[tid - o] : 0;
+    __syncthreads();
+    lds[tid] += y;
+    __syncthreads();
+  }
+  int64_t inc = lds[tid];
+  *total = lds[1023];
+  __syncthreads();
+  return inc - x;
+}
+
+__global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, const SceneAcc *sacc,
+                                                  const BodyAcc *bacc, SceneLay *slay,
+                                                  BodyLay *blay, Counters *cnt) {
+  __shared__ int64_t lds[1024];
+  int64_t carry_key = 0, carry_bmap = 0, carry_smap = 0;
+  for (int base = 0; base < ns; base += 1024) {
+    const int s = base + threadIdx.x;
+    int64_t key_sum = 0, bmap_sum = 0, smap_vol = 0;
+    if (s < ns) {
+      const SceneAcc a = sacc[s];
+      if (a.bmin[0] <= a.bmax[0]) {
+        smap_vol = 1;
+        for (int d = 0; d < 3; ++d) smap_vol *= (int64_t)(a.bmax[d] - a.bmin[d] + 2);
+      }
+      for (int b = 0; b <= a.max_body; ++b) {
+        const BodyAcc ba = bacc[sc[s].body_base + b];
+        if (ba.bmin[0] > ba.bmax[0]) continue;
+        int64_t kv = 1, mv = 1;
+        for (int d = 0; d < 3; ++d) {
+          int64_t e = (int64_t)(ba.bmax[d] - ba.bmin[d] + 1);
+          kv *= e;
+          mv *= e + 1;
+        }
+        key_sum += kv;
+        bmap_sum += mv;
+      }
+    }
+    int64_t tk, tb, ts;
+    int64_t ok_ = block_excl_scan64(key_sum, lds, &tk) + carry_key;
+    int64_t ob_ = block_excl_scan64(bmap_sum, lds, &tb) + carry_bmap;
+    int64_t os_ = block_excl_scan64(smap_vol, lds, &ts) + carry_smap;
+    if (s < ns) {
+      const SceneAcc a = sacc[s];
+      SceneLay L;
+      L.smap_off = os_;
+      for (int d = 0; d < 3; ++d) {
+        bool ne = a.bmin[0] <= a.bmax[0];
+        L.smin[d] = ne ? a.bmin[d] : 0;
+        L.sext[d] = ne ? a.bmax[d] - a.bmin[d] + 2 : 0;
+      }
+      slay[s] = L;
+      int64_t kcur = ok_, bcur = ob_;
+      for (int b = 0; b <= a.max_body; ++b) {
+        const int gb = sc[s].body_base + b;
+        const BodyAcc ba = bacc[gb];
+        BodyLay bl;
+        bl.scene = s;
+        bl.key_off = (int32_t)(kcur < kMaxKeyBlocks ? kcur : kMaxKeyBlocks);
+        bl.bmap_off = bcur;
+        if (ba.bmin[0] > ba.bmax[0]) {
+          for (int d = 0; d < 3; ++d) {
+            bl.bmin[d] = 0;
+            bl.ext[d] = 0;
+          }
+        } else {
+          int64_t kv = 1, mv = 1;
+          for (int d = 0; d < 3; ++d) {
+            bl.bmin[d] = ba.bmin[d];
+            bl.ext[d] = ba.bmax[d] - ba.bmin[d] + 1;
+            kv *= bl.ext[d];
+            mv *= bl.ext[d] + 1;
+          }
+          kcur += kv;
+          bcur += mv;
+        }
+        blay[gb] = bl;
+      }
+    }
+    carry_key += tk;
+    carry_bmap += tb;
+    carry_smap += ts;
+  }
+  if (threadIdx.x == 0) {
+    if (carry_key > kMaxKeyBlocks) atomicOr(&cnt->err, kErrKeyOverflow);
+    cnt->key_blocks = (int32_t)(carry_key < kMaxKeyBlocks ? carry_key : kMaxKeyBlocks);
+    cnt->smap_total = carry_smap;
+    cnt->bmap_total = carry_bmap;
+  }
+}
+
+void launch_domains(const SceneDev *sc, int ns, const SceneAcc *sacc, const BodyAcc *bacc,
+                    SceneLay *slay, BodyLay *blay, Counters *cnt, hipStream_t st) {
+  k_domains<<<1, 1024, 0, st>>>(sc, ns, sacc, bacc, slay, blay, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_keys(const T *x, const uint16_t *body, int64_t n,
+                                              const SceneDev *sc, int ns, const BodyLay *blay,
+                                              uint32_t *keys) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int s = scene_of(sc, ns, p);
+  const SceneDev sd = sc[s];
+  CellInfo ci = cell_of(x, n, p, sd);
+  const int b = body[p];
+  uint32_t key = 0;
+  if (ci.ok && b < sd.n_bodies) {
+    const BodyLay bl = blay[sd.body_base + b];
+    int32_t L[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) L[d] = floor_div4(ci.c[d]) - bl.bmin[d];
+    int64_t lin = (int64_t)bl.key_off + L[0] + (int64_t)bl.ext[0] * (L[1] + (int64_t)bl.ext[1] * L[2]);
+    int cib = (ci.c[0] & 3) | ((ci.c[1] & 3) << 2) | ((ci.c[2] & 3) << 4);
+    if (lin < kMaxKeyBlocks) key = (uint32_t)(lin * 64 + cib);
+  }
+  keys[p] = key;
+}
+
+template <typename T>
+void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
+                 const BodyLay *blay, uint32_t *keys, hipStream_t st) {
+  if (n <= 0) return;
+  k_keys<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x, body, n, sc, ns, blay, keys);
+}
+
+// ---------------------------------------------------------------------------
+// gather into sorted order (+ momentum before)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Accumulate kRed per-scene quantities (wave-aggregated when uniform).
+__device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed], double *red) {
+  const int lane = threadIdx.x & 63;
+  uint64_t valid = __ballot(ok);
+  if (valid == 0) return;
+  int first = __ffsll((unsigned long long)valid) - 1;
+  int s0 = __shfl(s, first, 64);
+  bool uniform = __ballot(ok && s != s0) == 0;
+  if (uniform) {
+#pragma unroll
+    for (int k = 0; k < kRed; ++k) {
+      double v = wave_sum(ok ? q[k] : 0.0);
+      if (lane == first) atomicAdd(&red[(int64_t)s0 * kRed + k], v);
+    }
+  } else if (ok) {
+#pragma unroll
+    for (int k = 0; k < kRed; ++k) atomicAdd(&red[(int64_t)s * kRed + k], q[k]);
+  }
+}
+
+// P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
+// particle count, unconstrained count (filled elsewhere).
+__device__ __forceinline__ void momentum_terms(const double r[3], const double v[3],
+                                               const double C[9], double m, double h,
+                                               double q[kRed]) {
+  const double k = 0.5 * h * h;
+  q[0] = m * v[0];
+  q[1] = m * v[1];
+  q[2] = m * v[2];
+  q[3] = m * (r[1] * v[2] - r[2] * v[1] + k * (C[7] - C[5]));
+  q[4] = m * (r[2] * v[0] - r[0] * v[2] + k * (C[2] - C[6]));
+  q[5] = m * (r[0] * v[1] - r[1] * v[0] + k * (C[3] - C[1]));
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  double c2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) c2 += C[a] * C[a];
+  q[6] = 0.5 * m * (v2 + k * c2);
+  q[7] = m * sqrt(v2);
+  q[8] = m * (sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * sqrt(v2) + k * sqrt(c2));
+  q[9] = 1.0;
+  q[10] = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, int64_t n, const T *x,
+                                                const T *v, const T *C, const T *m,
+                                                const uint16_t *body, const SceneDev *sc, int ns,
+                                                T *t_out, T *vbar_out, T *m_out,
+                                                int32_t *sbody_out, T *x_out, uint16_t *body_out,
+                                                double *red) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < n;
+  int s = 0;
+  double q[kRed];
+  if (ok) {
+    const int64_t p = perm[i];
+    s = scene_of(sc, ns, p);
+    const SceneDev sd = sc[s];
+    CellInfo ci = cell_of(x, n, p, sd);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) t_out[d * n + i] = (T)ci.t[d];
+    double vv[3], CC[9], r[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T val = v[d * n + p];
+      vbar_out[d * n + i] = val;
+      vv[d] = (double)val;
+      T xv = x[d * n + p];
+      r[d] = (double)xv - sd.origin[d];
+      if (x_out) x_out[d * n + i] = xv;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      T val = C[k * n + p];
+      vbar_out[(3 + k) * n + i] = val;
+      CC[k] = (double)val;
+    }
+    const T mv = m[p];
+    m_out[i] = mv;
+    const int b = body[p];
+    sbody_out[i] = sd.body_base + (b < sd.n_bodies ? b : 0);
+    if (body_out) body_out[i] = (uint16_t)b;
+    if (red) momentum_terms(r, vv, CC, (double)mv, sd.h, q);
+  }
+  if (red) reduce_scene(ok, s, q, red);
+}
+
+template <typename T>
+void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
+                   const T *m, const uint16_t *body, const SceneDev *sc, int ns, T *t_out,
+                   T *vbar_out, T *m_out, int32_t *sbody_out, T *x_out, uint16_t *body_out,
+                   double *red, hipStream_t st) {
+  if (n <= 0) return;
+  k_gather<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(perm, n, x, v, C, m, body, sc, ns,
+                                                            t_out, vbar_out, m_out, sbody_out,
+                                                            x_out, body_out, red);
+}
+
+// ---------------------------------------------------------------------------
+// segments and work items
+// ---------------------------------------------------------------------------
+__global__ void k_seg_flags(const uint32_t *keys, int64_t n, int32_t *flags) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = (i == 0 || (keys[i] >> 6) != (keys[i - 1] >> 6)) ? 1 : 0;
+}
+
+// flags have been scanned in place into seg ids; heads write segments.
+__global__ void k_seg_heads(const uint32_t *keys, int64_t n, const int32_t *segid,
+                            const int32_t *sbody, const BodyLay *blay, Segment *seg,
+                            int64_t seg_cap, Counters *cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool head = i == 0 || (keys[i] >> 6) != (keys[i - 1] >> 6);
+    if (!head) continue;
+    int32_t k = segid[i];
+    if (k >= seg_cap) {
+      atomicOr(&cnt->err, kErrCapacity);
+      continue;
+    }
+    const int gb = sbody[i];
+    const BodyLay bl = blay[gb];
+    int64_t local = (int64_t)(keys[i] >> 6) - bl.key_off;
+    int ex = bl.ext[0] > 0 ? bl.ext[0] : 1, ey = bl.ext[1] > 0 ? bl.ext[1] : 1;
+    int lx = (int)(local % ex);
+    int ly = (int)((local / ex) % ey);
+    int lz = (int)(local / ((int64_t)ex * ey));
+    Segment sg;
+    sg.start = (int32_t)i;
+    sg.count = 0;
+    sg.body = gb;
+    sg.scene = bl.scene;
+    sg.B[0] = bl.bmin[0] + lx;
+    sg.B[1] = bl.bmin[1] + ly;
+    sg.B[2] = bl.bmin[2] + lz;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sg.sslot[j] = -1;
+      sg.bslot[j] = -1;
+    }
+    seg[k] = sg;
+  }
+}
+
+// counts from consecutive starts; items per segment into tmp.
+__global__ void k_seg_counts(Segment *seg, int64_t seg_cap, const int64_t *nseg_dev, int64_t n,
+                             int32_t *nitems, Counters *cnt) {
+  int64_t ns = *nseg_dev;
+  if (ns > seg_cap) ns = seg_cap;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
+    int32_t c = (int32_t)(end - seg[k].start);
+    seg[k].count = c;
+    nitems[k] = (c + kItem - 1) / kItem;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_seg = (int32_t)ns;
+}
+
+__global__ void k_items(const Segment *seg, int64_t seg_cap, const int64_t *nseg_dev,
+                        const int32_t *item_off, Item *items, int64_t item_cap, Counters *cnt,
+                        const int64_t *nitems_dev) {
+  int64_t ns = *nseg_dev;
+  if (ns > seg_cap) ns = seg_cap;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const Segment sg = seg[k];
+    int32_t off = item_off[k];
+    for (int32_t s = 0; s < sg.count; s += kItem) {
+      int64_t w = off + s / kItem;
+      if (w >= item_cap) {
+        atomicOr(&cnt->err, kErrCapacity);
+        break;
+      }
+      Item it;
+      it.seg = (int32_t)k;
+      it.start = sg.start + s;
+      it.count = min(kItem, sg.count - s);
+      it.pad = 0;
+      items[w] = it;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t w = *nitems_dev;
+    cnt->n_items = (int32_t)(w < item_cap ? w : item_cap);
+  }
+}
+
+void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
+                     int64_t *tot, const int32_t *sbody, const BodyLay *blay, Segment *seg,
+                     int64_t seg_cap, Item *items, int64_t item_cap, int32_t *seg_tmp,
+                     Counters *cnt, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (g > 8192) g = 8192;
+  k_seg_flags<<<g, 256, 0, st>>>(keys, n, flags);
+  scan_exclusive(flags, flags, n, nullptr, &tot[0], partial, 0, st);
+  k_seg_heads<<<g, 256, 0, st>>>(keys, n, flags, sbody, blay, seg, seg_cap, cnt);
+  unsigned gs = (unsigned)((seg_cap + 255) / 256);
+  if (gs > 8192) gs = 8192;
+  k_seg_counts<<<gs, 256, 0, st>>>(seg, seg_cap, &tot[0], n, seg_tmp, cnt);
+  scan_exclusive(seg_tmp, seg_tmp, seg_cap, &tot[0], &tot[1], partial, 0, st);
+  k_items<<<gs, 256, 0, st>>>(seg, seg_cap, &tot[0], seg_tmp, items, item_cap, cnt, &tot[1]);
+}
+
+// ---------------------------------------------------------------------------
+// node-block maps
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t smap_index(const SceneLay &L, int bx, int by, int bz) {
+  int rx = bx - L.smin[0], ry = by - L.smin[1], rz = bz - L.smin[2];
+  return L.smap_off + rx + (int64_t)L.sext[0] * (ry + (int64_t)L.sext[1] * rz);
+}
+
+__device__ __forceinline__ int64_t bmap_index(const BodyLay &L, int bx, int by, int bz) {
+  int rx = bx - L.bmin[0], ry = by - L.bmin[1], rz = bz - L.bmin[2];
+  int64_t ex = L.ext[0] + 1, ey = L.ext[1] + 1;
+  return L.bmap_off + rx + ex * (ry + ey * rz);
+}
+
+__global__ void k_copy_totals(Counters *cnt, int64_t *tot) {
+  tot[5] = cnt->smap_total;
+  tot[6] = cnt->bmap_total;
+}
+
+__global__ void k_mark(const Segment *seg, const Counters *cnt, int64_t seg_cap,
+                       const SceneLay *slay, const BodyLay *blay, int32_t *smap, int64_t smap_cap,
+                       int32_t *bmap, int64_t bmap_cap) {
+  int64_t ns = cnt->n_seg;
+  if (ns > seg_cap) ns = seg_cap;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = q >> 3;
+    const int j = (int)(q & 7);
+    const Segment &sg = seg[k];
+    const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
+    int64_t si = smap_index(slay[sg.scene], bx, by, bz);
+    int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
+    if (si >= 0 && si < smap_cap) smap[si] = 1;
+    if (bi >= 0 && bi < bmap_cap) bmap[bi] = 1;
+  }
+}
+
+__global__ void k_seg_slots(Segment *seg, const Counters *cnt, int64_t seg_cap,
+                            const SceneLay *slay, const BodyLay *blay, const int32_t *smap,
+                            int64_t smap_cap, const int32_t *bmap, int64_t bmap_cap) {
+  int64_t ns = cnt->n_seg;
+  if (ns > seg_cap) ns = seg_cap;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = q >> 3;
+    const int j = (int)(q & 7);
+    Segment &sg = seg[k];
+    const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
+    int64_t si = smap_index(slay[sg.scene], bx, by, bz);
+    int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
+    sg.sslot[j] = (si >= 0 && si < smap_cap) ? smap[si] : -1;
+    sg.bslot[j] = (bi >= 0 && bi < bmap_cap) ? bmap[bi] : -1;
+  }
+}
+
+__global__ void k_block_counts(Counters *cnt, const int64_t *tot, int64_t sblk_cap,
+                               int64_t bblk_cap, int64_t smap_cap, int64_t bmap_cap) {
+  int64_t s = tot[2], b = tot[3];
+  int err = 0;
+  if (s > sblk_cap) err |= kErrCapacity;
+  if (b > bblk_cap) err |= kErrCapacity;
+  if (cnt->smap_total > smap_cap || cnt->bmap_total > bmap_cap) err |= kErrCapacity;
+  if (err) atomicOr(&cnt->err, err);
+  cnt->n_sblocks = (int32_t)(s < sblk_cap ? s : sblk_cap);
+  cnt->n_bblocks = (int32_t)(b < bblk_cap ? b : bblk_cap);
+}
+
+void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
+                 int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
+                 int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,
+                 int64_t bblk_cap, hipStream_t st) {
+  k_copy_totals<<<1, 1, 0, st>>>(cnt, tot);
+  fill_i32(smap, 0, smap_cap, &tot[5], 1, st);
+  fill_i32(bmap, 0, bmap_cap, &tot[6], 1, st);
+  unsigned g = (unsigned)((seg_cap * 8 + 255) / 256);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  k_mark<<<g, 256, 0, st>>>(seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
+  scan_exclusive(smap, smap, smap_cap, &tot[5], &tot[2], partial, 1, st);
+  scan_exclusive(bmap, bmap, bmap_cap, &tot[6], &tot[3], partial, 1, st);
+  k_seg_slots<<<g, 256, 0, st>>>(seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
+  k_block_counts<<<1, 1, 0, st>>>(cnt, tot, sblk_cap, bblk_cap, smap_cap, bmap_cap);
+}
+
+// explicit instantiations
+template void launch_cells<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
+                                  SceneAcc *, BodyAcc *, Counters *, hipStream_t);
+template void launch_cells<double>(const double *, const uint16_t *, int64_t, const SceneDev *,
+                                   int, SceneAcc *, BodyAcc *, Counters *, hipStream_t);
+template void launch_keys<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
+                                 const BodyLay *, uint32_t *, hipStream_t);
+template void launch_keys<double>(const double *, const uint16_t *, int64_t, const SceneDev *, int,
+                                  const BodyLay *, uint32_t *, hipStream_t);
+template void launch_gather<float>(const uint32_t *, int64_t, const float *, const float *,
+                                   const float *, const float *, const uint16_t *,
+                                   const SceneDev *, int, float *, float *, float *, int32_t *,
+                                   float *, uint16_t *, double *, hipStream_t);
+template void launch_gather<double>(const uint32_t *, int64_t, const double *, const double *,
+                                    const double *, const double *, const uint16_t *,
+                                    const SceneDev *, int, double *, double *, double *,
+                                    int32_t *, double *, uint16_t *, double *, hipStream_t);
+
+}  // namespace apic
