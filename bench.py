@@ -1,0 +1,222 @@
+"""Benchmark of the APIC augury contact step on one MI355X.
+
+Workload: the 64x64x16-particle block sliding on a 256x256x16-particle slab
+(1,114,112 particles, sparse grid h = 1, mu = 0.3, 4 augury iterations),
+stepped by the resident driver (contact step, then x += dt v) with state
+resident in HBM.  One "step" is one pass of the whole hot path: cell keys,
+radix sort, gather, segments and sparse node-block maps, mass and Vbar P2G,
+four fused G2P + friction-rule + P2G rounds, and the final G2P with drift.
+
+Prints ONE JSON line: FP32-mixed throughput (the headline value, graph
+replay), the plain FP64 throughput on the same scene, the roofline of the
+dominant kernel (the fused round kernel, timed with HIP events on its
+stream), and the CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "contact particle-steps/s (FP32-mixed vs plain FP64) at 2e-5 tol; %HBM peak; p99"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes of one fused round per particle (FP32-mixed; FP64 doubles
+# all but the 4-byte key): read
+# t (12) + key (4) + m (4) + normal (12) + series state Y (48), write Y (48);
+# per active grid node: read velocity (12) + write momentum (12).
+ROUND_BYTES_PER_PARTICLE = {"fp32": 128, "fp64": 252}
+ROUND_BYTES_PER_NODE = {"fp32": 24, "fp64": 48}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("transfer.hip", "apic_internal.h"):
+        with open(os.path.join(ROOT, "paper_2108_02259_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "round_kernel_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash() or d.get("kernel") != kernel:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mu", type=float, default=0.3)
+    ap.add_argument("--profile-steps", type=int, default=40)
+    ap.add_argument("--fp64-steps", type=int, default=60)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the contact step on a single "
+              "MI355X and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2108_02259_amd import scenes
+    from paper_2108_02259_amd.contact import Context, Sim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    sc = scenes.slab_block(mu=args.mu)
+    n = sc.n
+    log(f"scene slab_block n={n} mu={sc.mu} N={sc.n_iter} dt={sc.dt:.4f}")
+    table = [dict(offset=0, count=n, h=sc.h, origin=sc.origin, dims=sc.dims, mu=sc.mu,
+                  n_iter=sc.n_iter, n_bodies=sc.n_bodies)]
+    ctx = Context(0)
+    bt = torch.from_numpy(sc.body.view(np.int16).copy()).to(dev)
+
+    def make(dtype):
+        arrs = [torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).to(dev)
+                for a in (sc.x, sc.v, sc.C, sc.m)]
+        return Sim(ctx, table, [sc.dt], *arrs, bt)
+
+    def timed(sim, steps, graph):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps, graph=graph)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # ---- FP32-mixed: headline (graph replay) ----------------------------
+    use_graph = not args.no_graph
+    sim = make(np.float32)
+    sim.step(args.warmup, graph=use_graph)
+    t = timed(sim, args.steps, use_graph)
+    value = n * args.steps / t
+    ms_per_step = 1e3 * t / args.steps
+    log(f"fp32-mixed: {ms_per_step:.3f} ms/step, {value:.3e} particle-steps/s "
+        f"(graph={use_graph})")
+    reps, drift, steps_done = sim.report()
+    info = sim.info()
+    # ---- FP32-mixed: kernel durations from HIP events recorded inside the
+    # replayed step graph (one event pair around each kernel class, on the
+    # stream the kernels run on; the host waits after each replay) ----------
+    sim.profiling(True)
+    sim.kernel_times()
+    t_prof = timed(sim, args.profile_steps, use_graph)
+    kt = sim.kernel_times()
+    sim.profiling(False)
+    log(f"fp32-mixed with kernel events: {1e3 * t_prof / args.profile_steps:.3f} ms/step")
+    for k, (ms, cnt) in kt.items():
+        if cnt:
+            log(f"  {k:9s} {ms / cnt * 1e3:9.1f} us x {cnt / args.profile_steps:.0f}/step")
+    info = sim.info()
+    round_ms, round_cnt = kt["round"]
+    round_us = 1e3 * round_ms / max(round_cnt, 1)
+    nodes = info["shared_blocks"] * 64
+    alg_bytes = n * ROUND_BYTES_PER_PARTICLE["fp32"] + nodes * ROUND_BYTES_PER_NODE["fp32"]
+    achieved = alg_bytes / (round_us * 1e-6) / 1e9
+    traffic = traffic_from_profiles("apic::k_iter<float, false, false>")
+    max_drift = drift[0]
+    sim.close()
+
+    # ---- plain FP64 on the same scene --------------------------------------
+    sim64 = make(np.float64)
+    sim64.step(max(2, args.warmup // 4), graph=use_graph)
+    t64 = timed(sim64, args.fp64_steps, use_graph)
+    value64 = n * args.fp64_steps / t64
+    _, drift64, _ = sim64.report()
+    sim64.close()
+    log(f"fp64: {1e3 * t64 / args.fp64_steps:.3f} ms/step, {value64:.3e} particle-steps/s")
+
+    # ---- CPU oracle baseline + teacher-forced parity of one step ----------
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        from oracle import oracle as ora
+        x32 = [a.astype(np.float32) for a in (sc.x, sc.v, sc.C, sc.m)]
+        xt, vt, Ct, mt = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in x32)
+        ctx.contact_step(xt, vt, Ct, mt, bt, sc.h, mu=sc.mu, n_iter=sc.n_iter)
+        torch.cuda.synchronize()
+        g = ora.Grid(h=sc.h)
+        t0 = time.perf_counter()
+        ref = ora.contact_step(g, *[a.astype(np.float64) for a in x32[:3]],
+                               x32[3].astype(np.float64), sc.body, sc.mu, sc.n_iter)
+        tc = time.perf_counter() - t0
+        cpu = {"value": n / tc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"1 contact step of the full {n}-particle slab+block scene "
+                         f"(FP64, mu {sc.mu}, N {sc.n_iter}), {tc:.1f} s on {cpu_model()}"}
+        scale = np.abs(ref["v"]).max()
+        err = max(np.abs(vt.cpu().numpy() - ref["v"]).max(),
+                  sc.h * np.abs(Ct.cpu().numpy() - ref["C"]).max()) / scale
+        parity = {"fp32_mixed_step_rel_err": float(err), "tol": 2e-5, "pass": bool(err <= 2e-5)}
+        log(f"cpu oracle: {tc:.1f} s/step; fp32 parity {err:.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32-mixed (fp64 keys, grid velocity, normals, friction rule, reductions)",
+        "data": "synthetic",
+        "config": {"workload": "slab_block: 64x64x16 block sliding at (2,0,-0.5) on a 256x256x16 "
+                               "slab, 1,114,112 particles, sparse grid h=1, mu=0.3, N=4, "
+                               "dt=0.2h/|v|, resident driver", "particles": n,
+                   "mu": sc.mu, "n_iter": sc.n_iter, "graph": use_graph},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "apic::k_iter<float, false, false> (fused G2P + rule + P2G round)",
+                     "kernel_us": round_us, "alg_bytes_per_launch": alg_bytes,
+                     "active_nodes": nodes},
+        "cpu_baseline": cpu,
+        "fp64": {"value": value64, "unit": "particle-steps/s",
+                 "ms_per_step": 1e3 * t64 / args.fp64_steps, "steps": args.fp64_steps,
+                 "max_drift_P": drift64[0][0], "max_drift_L": drift64[0][1]},
+        "max_drift_P": max_drift[0],
+        "max_drift_L": max_drift[1],
+        "parity": parity,
+        "kernels_us": {k: (1e3 * ms / cnt if cnt else None) for k, (ms, cnt) in kt.items()},
+        "plan": info,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

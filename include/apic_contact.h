@@ -142,6 +142,72 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
                            const uint16_t *body_id, apic_precision prec,
                            uint32_t *keys_sorted, uint32_t *perm);
 
+/* ------------------------------------------------------------------------
+ * Resident time stepping.
+ *
+ * A sim owns device copies of a packed batch of scenes and advances them with
+ * the explicit driver of Section 2.2 (tau = dt, no mechanical acceleration):
+ * each step takes Vbar = V, sets V <- S(Vbar) (the contact step above, with
+ * each scene's mu and N) and then x <- x + dt v.  State stays in HBM between
+ * steps, in the library's sorted order; apic_sim_read returns it in the
+ * caller's original order.  Capacities are sized from the initial state with
+ * headroom; a step that would exceed them is replayed after the plan grows,
+ * so results never depend on the headroom.  Steps can be captured into HIP
+ * graphs (use_graph = 1) and replayed with no host synchronisation.
+ * ------------------------------------------------------------------------ */
+typedef struct apic_sim apic_sim;
+
+/* Copy the batch (same layout and rules as apic_contact_step_batched) into a
+ * new sim.  dt (host, n_scenes entries) is each scene's time step. */
+apic_status apic_sim_create(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                            int32_t n_scenes, int64_t n_total, const double *dt,
+                            const void *x, const void *v, const void *C, const void *m,
+                            const uint16_t *body_id, apic_precision prec, apic_sim **out);
+
+/* Advance every scene by n_steps driver steps; synchronises `stream` at the
+ * end to check for errors. */
+apic_status apic_sim_step(apic_sim *sim, void *stream, int32_t n_steps, int32_t use_graph);
+
+/* Copy the current state to caller arrays (device, caller order; any of the
+ * pointers may be NULL). */
+apic_status apic_sim_read(apic_sim *sim, void *stream, void *x, void *v, void *C);
+
+/* Report of the last step per scene (host, n_scenes entries; may be NULL),
+ * and the largest relative momentum drift of any step so far per scene:
+ * max_drift[2*s] = max |dP|/P_scale, max_drift[2*s + 1] = max |dL|/L_scale
+ * (host, 2*n_scenes entries; may be NULL).  Also returns the number of
+ * completed steps. */
+apic_status apic_sim_report(apic_sim *sim, apic_report *per_scene, double *max_drift,
+                            int64_t *steps_done);
+
+/* Kernel timing: when enabled, eager (non-graph) steps bracket each kernel
+ * class with HIP events on the step's stream.  apic_sim_kernel_times
+ * returns, per class (APIC_KC_*), the summed milliseconds and the number of
+ * launches since the last call, and resets them. */
+enum {
+  APIC_KC_LAYOUT = 0,   /* cells, boxes, key domains, keys */
+  APIC_KC_SORT = 1,     /* radix sort passes */
+  APIC_KC_GATHER = 2,   /* permute state into sorted order, momentum before */
+  APIC_KC_SEGMENTS = 3, /* segments, work items, node-block maps, grid clear */
+  APIC_KC_MASS = 4,     /* grid mass, per-body mass and contact normals */
+  APIC_KC_P2G0 = 5,     /* Vbar to grid */
+  APIC_KC_GRIDVEL = 6,  /* grid velocity */
+  APIC_KC_ROUND1 = 7,   /* first series round (G2P + rule + P2G) */
+  APIC_KC_ROUND = 8,    /* later series rounds (G2P + rule + P2G) */
+  APIC_KC_FINAL = 9,    /* final G2P and output */
+  APIC_KC_AFTER = 10,   /* momentum after the step, drift */
+  APIC_KC_COUNT = 11
+};
+apic_status apic_sim_set_profiling(apic_sim *sim, int32_t enable);
+apic_status apic_sim_kernel_times(apic_sim *sim, double *ms, int64_t *launches);
+
+/* Sizes of the sim's current plan: out[0] particles, out[1] active shared
+ * node blocks of the last step, out[2] active body node blocks, out[3]
+ * segments, out[4] work items, out[5] sort key bits, out[6] device bytes held. */
+apic_status apic_sim_info(apic_sim *sim, int64_t *out);
+
+void apic_sim_destroy(apic_sim *sim);
+
 /* Device bytes a context needs to run one scene of n particles spread over
  * about `blocks_hint` 4x4x4 cell blocks (0 = estimate from n); used by
  * admission control.  Pure host function. */

@@ -60,7 +60,21 @@ SIGNATURES = {
     "apic_sort_keys": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
                                       ctypes.c_int64, P, P, ctypes.c_int, P, P]),
     "apic_scene_footprint": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]),
+    "apic_sim_create": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
+                                       ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int,
+                                       ctypes.POINTER(P)]),
+    "apic_sim_step": (ctypes.c_int, [P, P, ctypes.c_int32, ctypes.c_int32]),
+    "apic_sim_read": (ctypes.c_int, [P, P, P, P, P]),
+    "apic_sim_report": (ctypes.c_int, [P, ctypes.POINTER(Report), P, ctypes.POINTER(ctypes.c_int64)]),
+    "apic_sim_set_profiling": (ctypes.c_int, [P, ctypes.c_int32]),
+    "apic_sim_kernel_times": (ctypes.c_int, [P, P, P]),
+    "apic_sim_info": (ctypes.c_int, [P, P]),
+    "apic_sim_destroy": (None, [P]),
 }
+
+# kernel classes reported by apic_sim_kernel_times
+KERNEL_CLASSES = ["layout", "sort", "gather", "segments", "mass", "p2g0", "gridvel", "round1",
+                  "round", "final", "after"]
 
 _lib = None
 

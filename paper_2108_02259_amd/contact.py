@@ -113,5 +113,85 @@ class Context:
         return (keys[:n].to(torch.int64) & mask), (perm[:n].to(torch.int64) & mask)
 
 
+def scene_table(scenes):
+    arr = (_lib.Scene * len(scenes))()
+    for i, s in enumerate(scenes):
+        arr[i].offset = int(s["offset"])
+        arr[i].count = int(s["count"])
+        arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
+        arr[i].mu = float(s.get("mu", 0.0))
+        arr[i].n_iter = int(s.get("n_iter", 0))
+        arr[i].n_bodies = int(s["n_bodies"])
+    return arr
+
+
+class Sim:
+    """Resident time stepping of a packed batch (apic_sim_*): each step sets
+    V <- S(V) and then x <- x + dt v, with state kept in HBM."""
+
+    def __init__(self, ctx: Context, scenes, dt, x, v, C, m, body):
+        n = _check_tensors(x, v, C, m, body)
+        self.n = n
+        self.ns = len(scenes)
+        self.dtype = x.dtype
+        self.device = x.device
+        arr = scene_table(scenes)
+        dts = (ctypes.c_double * self.ns)(*[float(d) for d in dt])
+        self._h = ctypes.c_void_p()
+        self._ctx = ctx
+        check(lib().apic_sim_create(ctx._h, _stream(), arr, self.ns, n, dts, _ptr(x), _ptr(v),
+                                    _ptr(C), _ptr(m), _ptr(body), precision_of(x),
+                                    ctypes.byref(self._h)), "apic_sim_create")
+
+    def step(self, n_steps: int = 1, graph: bool = False):
+        check(lib().apic_sim_step(self._h, _stream(), int(n_steps), int(bool(graph))),
+              "apic_sim_step")
+
+    def read(self):
+        x = torch.empty((3, self.n), dtype=self.dtype, device=self.device)
+        v = torch.empty((3, self.n), dtype=self.dtype, device=self.device)
+        C = torch.empty((9, self.n), dtype=self.dtype, device=self.device)
+        check(lib().apic_sim_read(self._h, _stream(), _ptr(x), _ptr(v), _ptr(C)), "apic_sim_read")
+        return x, v, C
+
+    def report(self):
+        reps = (_lib.Report * self.ns)()
+        drift = (ctypes.c_double * (2 * self.ns))()
+        steps = ctypes.c_int64()
+        check(lib().apic_sim_report(self._h, reps, ctypes.cast(drift, ctypes.c_void_p),
+                                    ctypes.byref(steps)), "apic_sim_report")
+        return ([_lib.report_dict(r) for r in reps],
+                [(drift[2 * s], drift[2 * s + 1]) for s in range(self.ns)], steps.value)
+
+    def profiling(self, on: bool):
+        check(lib().apic_sim_set_profiling(self._h, int(bool(on))), "apic_sim_set_profiling")
+
+    def kernel_times(self):
+        """{class: (total ms, launches)} since the last call."""
+        ms = (ctypes.c_double * len(_lib.KERNEL_CLASSES))()
+        cnt = (ctypes.c_int64 * len(_lib.KERNEL_CLASSES))()
+        check(lib().apic_sim_kernel_times(self._h, ctypes.cast(ms, ctypes.c_void_p),
+                                          ctypes.cast(cnt, ctypes.c_void_p)),
+              "apic_sim_kernel_times")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+    def info(self):
+        out = (ctypes.c_int64 * 8)()
+        check(lib().apic_sim_info(self._h, ctypes.cast(out, ctypes.c_void_p)), "apic_sim_info")
+        return {"n": out[0], "shared_blocks": out[1], "body_blocks": out[2], "segments": out[3],
+                "items": out[4], "sort_bits": out[5], "bytes": out[6]}
+
+    def close(self):
+        if self._h:
+            lib().apic_sim_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def footprint(n: int, blocks_hint: int = 0, precision: int = _lib.FP32_MIXED) -> int:
     return int(lib().apic_scene_footprint(int(n), int(blocks_hint), int(precision)))

@@ -1,5 +1,5 @@
-// api.hip -- context, workspace and the C ABI entry points of the contact
-// library (declared in include/apic_contact.h).
+// api.hip -- context, plans, the stateless contact step and the resident
+// (graph-capturable) driver behind the C ABI of include/apic_contact.h.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -10,6 +10,20 @@
 #include "kernels.h"
 
 using namespace apic;
+
+#define HIPOK(expr)                                   \
+  do {                                                \
+    if ((expr) != hipSuccess) {                       \
+      (void)hipGetLastError();                        \
+      return APIC_E_DEVICE;                           \
+    }                                                 \
+  } while (0)
+
+#define TRY(expr)                       \
+  do {                                  \
+    apic_status _s = (expr);            \
+    if (_s != APIC_OK) return _s;       \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // workspace
@@ -54,20 +68,6 @@ static apic_status status_from_err(int32_t err) {
   if (err & kErrCapacity) return APIC_E_DEVICE;
   return APIC_OK;
 }
-
-#define HIPOK(expr)                                   \
-  do {                                                \
-    if ((expr) != hipSuccess) {                       \
-      (void)hipGetLastError();                        \
-      return APIC_E_DEVICE;                           \
-    }                                                 \
-  } while (0)
-
-#define TRY(expr)                       \
-  do {                                  \
-    apic_status _s = (expr);            \
-    if (_s != APIC_OK) return _s;       \
-  } while (0)
 
 apic_status apic_ctx::host_stage(size_t bytes) {
   if (stage_bytes >= bytes) return APIC_OK;
@@ -121,12 +121,15 @@ apic_status validate_scenes(const apic_scene *scenes, int32_t ns, int64_t n_tota
 }
 
 // ---------------------------------------------------------------------------
-// the layout phase (cells, boxes, keys, sort) shared by every entry point
+// plan: tables, capacities and buffer pointers of one step
 // ---------------------------------------------------------------------------
-template <typename T>
-apic_status layout_phase(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes, int32_t ns,
-                         int64_t n, const T *x, const uint16_t *body, LayoutResult *out) {
-  Workspace &W = ctx->ws;
+static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_scene *scenes,
+                               int32_t ns, int64_t n, apic_precision prec, const double *dt,
+                               hipStream_t st) {
+  P.prec = prec;
+  P.tbytes = prec == APIC_FP64 ? 8 : 4;
+  P.n = n;
+  P.ns = ns;
   std::vector<SceneDev> sd(ns);
   int64_t nb_cap = 0;
   int32_t kmax = 0;
@@ -138,6 +141,7 @@ apic_status layout_phase(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes
     }
     d.h = scenes[s].grid.h;
     d.mu = scenes[s].mu;
+    d.dt = dt ? dt[s] : 0.0;
     d.offset = scenes[s].offset;
     d.count = scenes[s].count;
     d.n_iter = scenes[s].n_iter;
@@ -147,8 +151,8 @@ apic_status layout_phase(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes
     kmax = std::max(kmax, scenes[s].n_iter);
     sd[s] = d;
   }
-  out->nb_cap = nb_cap;
-  out->max_iter = kmax;
+  P.nb_cap = nb_cap;
+  P.max_iter = kmax;
   TRY(W.ensure(kScenes, sizeof(SceneDev) * ns));
   TRY(W.ensure(kSceneAcc, sizeof(SceneAcc) * ns));
   TRY(W.ensure(kSceneLay, sizeof(SceneLay) * ns));
@@ -156,175 +160,406 @@ apic_status layout_phase(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes
   TRY(W.ensure(kBodyLay, sizeof(BodyLay) * nb_cap));
   TRY(W.ensure(kCounters, sizeof(Counters)));
   TRY(W.ensure(kTot, sizeof(int64_t) * 16));
-  TRY(ctx->host_stage(std::max(sizeof(SceneDev) * ns, sizeof(Counters))));
+  TRY(W.ensure(kRedBuf, sizeof(double) * kRed * 2 * ns));
+  TRY(W.ensure(kBoxRec, sizeof(BoxRec) * std::max<int64_t>(wave_records(n), 1)));
+  P.box_rec = (BoxRec *)W.ptr[kBoxRec];
+  P.sc = (SceneDev *)W.ptr[kScenes];
+  P.sacc = (SceneAcc *)W.ptr[kSceneAcc];
+  P.slay = (SceneLay *)W.ptr[kSceneLay];
+  P.bacc = (BodyAcc *)W.ptr[kBodyAcc];
+  P.blay = (BodyLay *)W.ptr[kBodyLay];
+  P.cnt = (Counters *)W.ptr[kCounters];
+  P.tot = (int64_t *)W.ptr[kTot];
+  P.red = (double *)W.ptr[kRedBuf];
+  TRY(ctx->host_stage(sizeof(SceneDev) * ns));
   std::memcpy(ctx->stage, sd.data(), sizeof(SceneDev) * ns);
-  HIPOK(hipMemcpyAsync(W.ptr[kScenes], ctx->stage, sizeof(SceneDev) * ns, hipMemcpyHostToDevice,
-                       st));
-  SceneDev *dsc = (SceneDev *)W.ptr[kScenes];
-  SceneAcc *sacc = (SceneAcc *)W.ptr[kSceneAcc];
-  BodyAcc *bacc = (BodyAcc *)W.ptr[kBodyAcc];
-  Counters *cnt = (Counters *)W.ptr[kCounters];
-  launch_layout_init(sacc, ns, bacc, (int)nb_cap, cnt, st);
-  launch_cells<T>(x, body, n, dsc, ns, sacc, bacc, cnt, st);
-  launch_domains(dsc, ns, sacc, bacc, (SceneLay *)W.ptr[kSceneLay], (BodyLay *)W.ptr[kBodyLay],
-                 cnt, st);
-  HIPOK(hipMemcpyAsync(ctx->stage, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  HIPOK(hipStreamSynchronize(st));
-  Counters c;
-  std::memcpy(&c, ctx->stage, sizeof(Counters));
-  TRY(status_from_err(c.err));
-  out->key_blocks = c.key_blocks;
-  out->smap_total = c.smap_total;
-  out->bmap_total = c.bmap_total;
-  // keys and sort
-  const int64_t ntiles = sort_tiles(n);
+  HIPOK(hipMemcpyAsync(P.sc, ctx->stage, sizeof(SceneDev) * ns, hipMemcpyHostToDevice, st));
+  HIPOK(hipStreamSynchronize(st));  // the staging buffer is reused right after
+  return APIC_OK;
+}
+
+// Capacities from the sizes of a measured layout (times `headroom`), then
+// every buffer of the step.
+static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t key_blocks,
+                                int64_t smap_total, int64_t bmap_total, double headroom) {
+  const int64_t n = P.n;
+  int64_t kb = std::max<int64_t>(1, (int64_t)std::ceil(key_blocks * headroom));
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) < kb * 64) ++bits;
+  P.sort_bits = bits;
+  P.smap_cap = std::max<int64_t>(1, (int64_t)std::ceil(smap_total * headroom));
+  P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
+  P.seg_cap = std::max<int64_t>(n, 1);
+  P.item_cap = n + n / kItem + 1;
+  P.sblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.smap_cap, 8 * n));
+  P.bblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.bmap_cap, 8 * n));
+  P.grid_wg = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->persistent_wg, (n + 63) / 64 * 2));
+  const int64_t ntiles = std::max<int64_t>(sort_tiles(n), 1);
+  const size_t T = P.tbytes;
   TRY(W.ensure(kKeysA, sizeof(uint32_t) * n));
   TRY(W.ensure(kValsA, sizeof(uint32_t) * n));
   TRY(W.ensure(kKeysB, sizeof(uint32_t) * n));
   TRY(W.ensure(kValsB, sizeof(uint32_t) * n));
-  TRY(W.ensure(kHist, sizeof(uint32_t) * 256 * std::max<int64_t>(ntiles, 1)));
-  int64_t pcap = std::max(scan_partials_needed(256 * std::max<int64_t>(ntiles, 1)),
+  TRY(W.ensure(kHist, sizeof(uint32_t) * 256 * ntiles));
+  int64_t pcap = std::max(scan_partials_needed(256 * ntiles),
                           scan_partials_needed(std::max<int64_t>(
-                              {n * 2, out->smap_total, out->bmap_total, (int64_t)1})));
+                              {n * 2, P.smap_cap, P.bmap_cap, (int64_t)1})));
   TRY(W.ensure(kPartial, sizeof(int32_t) * pcap));
-  launch_keys<T>(x, body, n, dsc, ns, (const BodyLay *)W.ptr[kBodyLay], (uint32_t *)W.ptr[kKeysA],
-                 st);
-  int64_t key_space = (int64_t)std::max(out->key_blocks, 1) * 64;
-  int bits = 1;
-  while (bits < 32 && ((int64_t)1 << bits) < key_space) ++bits;
-  out->sort_bits = bits;
-  int where = 0;
-  if (n > 0)
-    where = radix_sort((uint32_t *)W.ptr[kKeysA], (uint32_t *)W.ptr[kValsA],
-                       (uint32_t *)W.ptr[kKeysB], (uint32_t *)W.ptr[kValsB], n, bits,
-                       (uint32_t *)W.ptr[kHist], (int32_t *)W.ptr[kPartial],
-                       (int64_t *)W.ptr[kTot] + 9, st);
-  out->keys = (uint32_t *)W.ptr[where ? kKeysB : kKeysA];
-  out->perm = (uint32_t *)W.ptr[where ? kValsB : kValsA];
+  TRY(W.ensure(kT, T * 3 * n));
+  TRY(W.ensure(kMs, T * n));
+  TRY(W.ensure(kSbody, sizeof(int32_t) * n));
+  TRY(W.ensure(kNrm, T * 3 * n));
+  TRY(W.ensure(kY, T * 12 * n));
+  TRY(W.ensure(kSeg, sizeof(Segment) * P.seg_cap));
+  TRY(W.ensure(kSegTmp, sizeof(int32_t) * (P.seg_cap + 1)));
+  TRY(W.ensure(kFlags, sizeof(int32_t) * n));
+  TRY(W.ensure(kItems, sizeof(Item) * P.item_cap));
+  TRY(W.ensure(kSmap, sizeof(int32_t) * P.smap_cap));
+  TRY(W.ensure(kBmap, sizeof(int32_t) * P.bmap_cap));
+  TRY(W.ensure(kGMass, T * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kGBuf0, T * 3 * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kGBuf1, T * 3 * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kBMass, sizeof(double) * kNodesPerBlock * P.bblk_cap));
+  TRY(W.ensure(kRecGather, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
+  TRY(W.ensure(kRecItems, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
+  P.rec_gather = (RedRec *)W.ptr[kRecGather];
+  P.rec_items = (RedRec *)W.ptr[kRecItems];
+  P.ka = (uint32_t *)W.ptr[kKeysA];
+  P.va = (uint32_t *)W.ptr[kValsA];
+  P.kb = (uint32_t *)W.ptr[kKeysB];
+  P.vb = (uint32_t *)W.ptr[kValsB];
+  P.hist = (uint32_t *)W.ptr[kHist];
+  P.partial = (int32_t *)W.ptr[kPartial];
+  P.t = W.ptr[kT];
+  P.ms = W.ptr[kMs];
+  P.sbody = (int32_t *)W.ptr[kSbody];
+  P.nrm = W.ptr[kNrm];
+  P.Y = W.ptr[kY];
+  P.seg = (Segment *)W.ptr[kSeg];
+  P.segtmp = (int32_t *)W.ptr[kSegTmp];
+  P.flags = (int32_t *)W.ptr[kFlags];
+  P.items = (Item *)W.ptr[kItems];
+  P.smap = (int32_t *)W.ptr[kSmap];
+  P.bmap = (int32_t *)W.ptr[kBmap];
+  P.g.mass = W.ptr[kGMass];
+  P.g.buf[0] = W.ptr[kGBuf0];
+  P.g.buf[1] = W.ptr[kGBuf1];
+  P.g.bmass = (double *)W.ptr[kBMass];
+  P.ready = true;
   return APIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// enqueue helpers (no host synchronisation inside)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
+                           const int32_t *sticky, bool check_caps) {
+  launch_layout_init(P.sacc, P.ns, P.bacc, (int)P.nb_cap, P.cnt, st);
+  if (sticky) launch_copy_sticky(P.cnt, sticky, st);
+  launch_cells<T>(x, body, P.n, P.sc, P.ns, P.bacc, P.box_rec, P.cnt, st);
+  launch_reduce_box(P.box_rec, wave_records(P.n), P.bacc, st);
+  launch_domains(P.sc, P.ns, (int)P.nb_cap, P.sacc, P.bacc, P.slay, P.blay, P.cnt,
+                 check_caps ? P.sort_bits : 0, check_caps ? P.smap_cap : 0,
+                 check_caps ? P.bmap_cap : 0, st);
+}
+
+// keys + sort; sets P.keys / P.perm
+template <typename T>
+static void enqueue_sort(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
+                         Profiler *prof) {
+  launch_keys<T>(x, body, P.n, P.sc, P.ns, P.blay, P.ka, st);
+  if (prof) prof->end(APIC_KC_LAYOUT, st), prof->begin(st);
+  int where = radix_sort(P.ka, P.va, P.kb, P.vb, P.n, P.sort_bits, P.hist, P.partial, P.tot + 9,
+                         st);
+  if (prof) prof->end(APIC_KC_SORT, st);
+  P.keys = where ? P.kb : P.ka;
+  P.perm = where ? P.vb : P.va;
+}
+
+// Everything after the sort.  Source arrays are read through P.perm; outputs
+// go to (v_out, C_out) at perm positions (stateless) or in place in sorted
+// order with drift (resident, perm_out = false).
+template <typename T>
+static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const T *C, const T *m,
+                         const uint16_t *body, T *vbar, T *x_sorted, uint16_t *body_sorted,
+                         T *m_sorted, const uint32_t *orig_in, uint32_t *orig_out,
+                         T *v_out, T *C_out, bool unpermute, Profiler *prof) {
+  const int64_t n = P.n;
+  if (prof) prof->begin(st);
+  fill_bytes_zero(P.red, sizeof(double) * kRed * 2 * P.ns, st);
+  launch_gather<T>(P.perm, n, x, v, C, m, body, P.sc, P.ns, (T *)P.t, vbar, m_sorted, P.sbody,
+                   x_sorted, body_sorted, orig_in, orig_out, P.rec_gather, P.red, st);
+  launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
+  if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
+  launch_segments(P.keys, n, P.flags, P.partial, P.tot, P.sbody, P.blay, P.seg, P.seg_cap,
+                  P.items, P.item_cap, P.segtmp, P.cnt, st);
+  launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smap, P.smap_cap, P.bmap, P.bmap_cap,
+              P.partial, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
+  fill_zero_f(P.g.mass, P.sblk_cap, &P.cnt->n_sblocks, kNodesPerBlock, sizeof(T), st);
+  fill_zero_f(P.g.buf[0], P.sblk_cap, &P.cnt->n_sblocks, 3 * kNodesPerBlock, sizeof(T), st);
+  fill_zero_f(P.g.bmass, P.bblk_cap, &P.cnt->n_bblocks, kNodesPerBlock, sizeof(double), st);
+  if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
+  StepArgs a;
+  a.sc = P.sc;
+  a.seg = P.seg;
+  a.items = P.items;
+  a.cnt = P.cnt;
+  a.keys = P.keys;
+  a.n = n;
+  a.grid_wg = P.grid_wg;
+  const T *t = (const T *)P.t;
+  T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
+  launch_mass<T>(a, t, m_sorted, P.g, st);
+  if (P.max_iter > 0) launch_normals<T>(a, t, nrm, P.g, st);
+  if (prof) prof->end(APIC_KC_MASS, st), prof->begin(st);
+  launch_p2g0<T>(a, t, m_sorted, vbar, P.g, st);
+  if (prof) prof->end(APIC_KC_P2G0, st), prof->begin(st);
+  launch_gridvel<T>(a, P.g, 0, st);
+  if (prof) prof->end(APIC_KC_GRIDVEL, st);
+  const uint32_t *perm_out = unpermute ? P.perm : nullptr;
+  int cur = 0;
+  for (int k = 1; k <= P.max_iter + 1; ++k) {
+    const bool final = k == P.max_iter + 1;
+    if (prof) prof->begin(st);
+    launch_iter<T>(a, k, final, t, m_sorted, vbar, nrm, Y, P.g, cur, perm_out, v_out, C_out, st);
+    if (prof) prof->end(final ? APIC_KC_FINAL : (k == 1 ? APIC_KC_ROUND1 : APIC_KC_ROUND), st);
+    if (final) break;
+    if (prof) prof->begin(st);
+    launch_gridvel<T>(a, P.g, 1 - cur, st);
+    if (prof) prof->end(APIC_KC_GRIDVEL, st);
+    cur = 1 - cur;
+  }
+  // momentum after (FP64) and, for the resident driver, the drift
+  if (prof) prof->begin(st);
+  T *x_after = unpermute ? (T *)x : x_sorted;
+  launch_after<T>(n, perm_out, x_after, v_out, C_out, m_sorted, nrm, P.sbody, P.blay, P.sc, P.cnt,
+                  unpermute ? 0 : 1, P.rec_items, P.red + kRed * P.ns, st);
+  launch_reduce_red(P.rec_items, wave_records(n), nullptr, P.cnt, P.red + kRed * P.ns, st);
+  if (prof) prof->end(APIC_KC_AFTER, st);
+}
+
+static void fill_report(const double *r, int ns, const Counters &c, apic_report *reports) {
+  for (int s = 0; s < ns; ++s) {
+    apic_report &R = reports[s];
+    const double *b = r + kRed * s, *af = r + kRed * (ns + s);
+    for (int d = 0; d < 3; ++d) {
+      R.P_before[d] = b[d];
+      R.L_before[d] = b[3 + d];
+      R.P_after[d] = af[d];
+      R.L_after[d] = af[3 + d];
+    }
+    R.E_before = b[6];
+    R.E_after = af[6];
+    R.P_scale = b[7];
+    R.L_scale = b[8];
+    R.n_particles = (int64_t)llround(b[9]);
+    R.n_unconstrained = (int64_t)llround(af[10]);
+    R.grid_blocks = c.n_sblocks;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // the stateless contact step
 // ---------------------------------------------------------------------------
 template <typename T>
-apic_status step_impl(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes, int32_t ns,
-                      int64_t n, const T *x, T *v, T *C, const T *m, const uint16_t *body,
-                      apic_report *reports) {
+static apic_status step_impl(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes, int32_t ns,
+                             int64_t n, const T *x, T *v, T *C, const T *m, const uint16_t *body,
+                             apic_report *reports) {
   Workspace &W = ctx->ws;
-  LayoutResult L;
-  TRY(layout_phase<T>(ctx, st, scenes, ns, n, x, body, &L));
+  Plan P;
+  TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED,
+                  nullptr, st));
   if (n == 0) {
     if (reports)
       for (int s = 0; s < ns; ++s) std::memset(&reports[s], 0, sizeof(apic_report));
     return APIC_OK;
   }
-  SceneDev *dsc = (SceneDev *)W.ptr[kScenes];
-  Counters *cnt = (Counters *)W.ptr[kCounters];
-  int64_t *tot = (int64_t *)W.ptr[kTot];
-  // sorted particle state
-  TRY(W.ensure(kT, sizeof(T) * 3 * n));
+  enqueue_prefix<T>(P, st, x, body, nullptr, false);
+  Counters c;
+  TRY(ctx->host_stage(sizeof(Counters)));
+  HIPOK(hipMemcpyAsync(ctx->stage, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  std::memcpy(&c, ctx->stage, sizeof(Counters));
+  TRY(status_from_err(c.err));
+  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0));
   TRY(W.ensure(kVbar, sizeof(T) * 12 * n));
-  TRY(W.ensure(kMs, sizeof(T) * n));
-  TRY(W.ensure(kSbody, sizeof(int32_t) * n));
-  TRY(W.ensure(kNrm, sizeof(T) * 3 * n));
-  TRY(W.ensure(kY, sizeof(T) * 12 * n));
-  TRY(W.ensure(kRedBuf, sizeof(double) * kRed * 2 * ns));
-  double *red = (double *)W.ptr[kRedBuf];
-  fill_bytes_zero(red, sizeof(double) * kRed * 2 * ns, st);
-  launch_gather<T>(L.perm, n, x, v, C, m, body, dsc, ns, (T *)W.ptr[kT], (T *)W.ptr[kVbar],
-                   (T *)W.ptr[kMs], (int32_t *)W.ptr[kSbody], nullptr, nullptr, red, st);
-  // segments, items, maps
-  const int64_t seg_cap = n;
-  const int64_t item_cap = n + n / kItem + 1;
-  TRY(W.ensure(kSeg, sizeof(Segment) * seg_cap));
-  TRY(W.ensure(kSegTmp, sizeof(int32_t) * (seg_cap + 1)));
-  TRY(W.ensure(kFlags, sizeof(int32_t) * n));
-  TRY(W.ensure(kItems, sizeof(Item) * item_cap));
-  const int64_t smap_cap = std::max<int64_t>(L.smap_total, 1);
-  const int64_t bmap_cap = std::max<int64_t>(L.bmap_total, 1);
-  TRY(W.ensure(kSmap, sizeof(int32_t) * smap_cap));
-  TRY(W.ensure(kBmap, sizeof(int32_t) * bmap_cap));
-  const int64_t sblk_cap = std::max<int64_t>(1, std::min<int64_t>(L.smap_total, 8 * n));
-  const int64_t bblk_cap = std::max<int64_t>(1, std::min<int64_t>(L.bmap_total, 8 * n));
-  TRY(W.ensure(kGMass, sizeof(T) * kNodesPerBlock * sblk_cap));
-  TRY(W.ensure(kGBuf0, sizeof(T) * 3 * kNodesPerBlock * sblk_cap));
-  TRY(W.ensure(kGBuf1, sizeof(T) * 3 * kNodesPerBlock * sblk_cap));
-  TRY(W.ensure(kBMass, sizeof(double) * kNodesPerBlock * bblk_cap));
-  Segment *seg = (Segment *)W.ptr[kSeg];
-  Item *items = (Item *)W.ptr[kItems];
-  int32_t *partial = (int32_t *)W.ptr[kPartial];
-  launch_segments(L.keys, n, (int32_t *)W.ptr[kFlags], partial, tot,
-                  (const int32_t *)W.ptr[kSbody], (const BodyLay *)W.ptr[kBodyLay], seg, seg_cap,
-                  items, item_cap, (int32_t *)W.ptr[kSegTmp], cnt, st);
-  launch_maps(seg, seg_cap, (const SceneLay *)W.ptr[kSceneLay], (const BodyLay *)W.ptr[kBodyLay],
-              (int32_t *)W.ptr[kSmap], smap_cap, (int32_t *)W.ptr[kBmap], bmap_cap, partial, tot,
-              cnt, sblk_cap, bblk_cap, st);
-  // transfers
-  GridPtrs g;
-  g.mass = W.ptr[kGMass];
-  g.buf[0] = W.ptr[kGBuf0];
-  g.buf[1] = W.ptr[kGBuf1];
-  g.bmass = (double *)W.ptr[kBMass];
-  fill_zero_f(g.mass, sblk_cap, &cnt->n_sblocks, kNodesPerBlock, sizeof(T), st);
-  fill_zero_f(g.buf[0], sblk_cap, &cnt->n_sblocks, 3 * kNodesPerBlock, sizeof(T), st);
-  fill_zero_f(g.bmass, bblk_cap, &cnt->n_bblocks, kNodesPerBlock, sizeof(double), st);
-  StepArgs a;
-  a.sc = dsc;
-  a.seg = seg;
-  a.items = items;
-  a.cnt = cnt;
-  a.keys = L.keys;
-  a.n = n;
-  a.grid_wg = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->persistent_wg, (n + 63) / 64 * 2));
-  const T *t = (const T *)W.ptr[kT];
-  const T *ms = (const T *)W.ptr[kMs];
-  const T *vbar = (const T *)W.ptr[kVbar];
-  T *nrm = (T *)W.ptr[kNrm];
-  T *Y = (T *)W.ptr[kY];
-  launch_p2g0<T>(a, t, ms, vbar, g, st);
-  launch_gridvel<T>(a, g, 0, st);
-  int cur = 0;
-  for (int k = 1; k <= L.max_iter; ++k) {
-    launch_iter<T>(a, k, t, ms, vbar, nrm, Y, g, cur, L.perm, v, C, nullptr, 0.0,
-                   red + kRed * ns, st);
-    launch_gridvel<T>(a, g, 1 - cur, st);
-    cur = 1 - cur;
-  }
-  launch_iter<T>(a, L.max_iter + 1, t, ms, vbar, nrm, Y, g, cur, L.perm, v, C, nullptr, 0.0,
-                 red + kRed * ns, st);
-  // results
+  enqueue_sort<T>(P, st, x, body, nullptr);
+  enqueue_body<T>(P, st, x, v, C, m, body, (T *)W.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
+                  nullptr, nullptr, v, C, true, nullptr);
   const size_t rbytes = sizeof(double) * kRed * 2 * ns;
   TRY(ctx->host_stage(rbytes + sizeof(Counters)));
-  HIPOK(hipMemcpyAsync(ctx->stage, red, rbytes, hipMemcpyDeviceToHost, st));
-  HIPOK(hipMemcpyAsync((char *)ctx->stage + rbytes, cnt, sizeof(Counters), hipMemcpyDeviceToHost,
-                       st));
+  HIPOK(hipMemcpyAsync(ctx->stage, P.red, rbytes, hipMemcpyDeviceToHost, st));
+  HIPOK(hipMemcpyAsync((char *)ctx->stage + rbytes, P.cnt, sizeof(Counters),
+                       hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
-  Counters c;
   std::memcpy(&c, (char *)ctx->stage + rbytes, sizeof(Counters));
   TRY(status_from_err(c.err));
-  ctx->last_sblocks = c.n_sblocks;
-  if (reports) {
-    const double *r = (const double *)ctx->stage;
-    for (int s = 0; s < ns; ++s) {
-      apic_report &R = reports[s];
-      const double *b = r + kRed * s, *af = r + kRed * (ns + s);
-      for (int d = 0; d < 3; ++d) {
-        R.P_before[d] = b[d];
-        R.L_before[d] = b[3 + d];
-        R.P_after[d] = af[d];
-        R.L_after[d] = af[3 + d];
-      }
-      R.E_before = b[6];
-      R.E_after = af[6];
-      R.P_scale = b[7];
-      R.L_scale = b[8];
-      R.n_particles = (int64_t)llround(b[9]);
-      R.n_unconstrained = (int64_t)llround(af[10]);
-      R.grid_blocks = c.n_sblocks;
+  if (c.err) return APIC_E_DEVICE;
+  if (reports) fill_report((const double *)ctx->stage, ns, c, reports);
+  return APIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiler: an event pair per kernel launch of eager steps
+// ---------------------------------------------------------------------------
+namespace apic {
+thread_local LaunchTimer *g_launch_timer = nullptr;
+}
+
+void Profiler::events(hipEvent_t *start, hipEvent_t *stop) {
+  if (free_events.size() < 2)
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) == hipSuccess) free_events.push_back(e);
     }
+  *start = free_events.back();
+  free_events.pop_back();
+  *stop = free_events.back();
+  free_events.pop_back();
+  recs.push_back({-1, *start, *stop});
+}
+
+void Profiler::begin(hipStream_t) {
+  if (!on) return;
+  open_from = recs.size();
+  g_launch_timer = this;
+}
+
+void Profiler::end(int kind, hipStream_t) {
+  if (!on) return;
+  for (size_t i = open_from; i < recs.size(); ++i) recs[i].kind = kind;
+  g_launch_timer = nullptr;
+  if (recs.size() > 8192) collect();
+}
+
+void Profiler::collect() {
+  for (auto &r : recs) {
+    (void)hipEventSynchronize(r.stop);
+    float ms = 0.f;
+    if (r.kind >= 0 && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      total_ms[r.kind] += ms;
+      launches[r.kind] += 1;
+    }
+    free_events.push_back(r.start);
+    free_events.push_back(r.stop);
+  }
+  recs.clear();
+  open_from = 0;
+}
+
+void Profiler::release() {
+  collect();
+  for (auto e : free_events) (void)hipEventDestroy(e);
+  free_events.clear();
+}
+
+// ---------------------------------------------------------------------------
+// resident driver
+// ---------------------------------------------------------------------------
+template <typename T>
+static void enqueue_sim_step(apic_sim *S, hipStream_t st, int parity, Profiler *prof) {
+  Plan &P = S->plan;
+  const int64_t n = P.n;
+  SimState &A = S->state[parity], &B = S->state[1 - parity];
+  if (prof) prof->begin(st);
+  enqueue_prefix<T>(P, st, (const T *)A.x, A.body, &S->dev->sticky, true);
+  enqueue_sort<T>(P, st, (const T *)A.x, A.body, prof);
+  T *vc = (T *)B.vc;
+  enqueue_body<T>(P, st, (const T *)A.x, (const T *)A.vc, (const T *)A.vc + 3 * n,
+                  (const T *)A.m, A.body, vc, (T *)B.x, B.body, (T *)B.m, A.orig, B.orig, vc,
+                  vc + 3 * n, false, prof);
+  launch_step_end(P.cnt, P.red, P.ns, S->dev, S->drift, st);
+}
+
+static apic_status sim_capture(apic_sim *S, hipStream_t st);
+
+template <typename T>
+static apic_status sim_run(apic_sim *S, hipStream_t st, int32_t n_steps, int use_graph) {
+  for (int32_t i = 0; i < n_steps; ++i) {
+    if (use_graph && !S->prof.on) {
+      if (!S->graph_ok) TRY(sim_capture(S, st));
+      HIPOK(hipGraphLaunch(S->exec[S->parity], st));
+    } else {
+      enqueue_sim_step<T>(S, st, S->parity, S->prof.on ? &S->prof : nullptr);
+    }
+    S->parity ^= 1;
   }
   return APIC_OK;
+}
+
+static apic_status sim_capture(apic_sim *S, hipStream_t st) {
+  for (int p = 0; p < 2; ++p) {
+    if (S->exec[p]) {
+      (void)hipGraphExecDestroy(S->exec[p]);
+      S->exec[p] = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPOK(hipStreamBeginCapture(S->capture_stream, hipStreamCaptureModeThreadLocal));
+    if (S->plan.prec == APIC_FP64)
+      enqueue_sim_step<double>(S, S->capture_stream, p, nullptr);
+    else
+      enqueue_sim_step<float>(S, S->capture_stream, p, nullptr);
+    HIPOK(hipStreamEndCapture(S->capture_stream, &g));
+    hipError_t e = hipGraphInstantiate(&S->exec[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return APIC_E_DEVICE;
+    }
+  }
+  (void)st;
+  S->graph_ok = true;
+  return APIC_OK;
+}
+
+static apic_status sim_read_dev(apic_sim *S, hipStream_t st, SimDev *out) {
+  TRY(S->ctx->host_stage(sizeof(SimDev)));
+  HIPOK(hipMemcpyAsync(S->ctx->stage, S->dev, sizeof(SimDev), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  std::memcpy(out, S->ctx->stage, sizeof(SimDev));
+  return APIC_OK;
+}
+
+// Measure the current layout, then size the plan with headroom.
+template <typename T>
+static apic_status sim_plan(apic_sim *S, hipStream_t st, double headroom) {
+  Plan &P = S->plan;
+  SimState &A = S->state[S->parity];
+  enqueue_prefix<T>(P, st, (const T *)A.x, A.body, nullptr, false);
+  Counters c;
+  TRY(S->ctx->host_stage(sizeof(Counters)));
+  HIPOK(hipMemcpyAsync(S->ctx->stage, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  std::memcpy(&c, S->ctx->stage, sizeof(Counters));
+  TRY(status_from_err(c.err));
+  TRY(plan_buffers(S->ctx, S->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom));
+  S->graph_ok = false;
+  return APIC_OK;
+}
+
+static apic_status sim_step_impl(apic_sim *S, hipStream_t st, int32_t n_steps, int use_graph) {
+  const bool f64 = S->plan.prec == APIC_FP64;
+  int64_t target = S->steps_done + n_steps;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    int32_t todo = (int32_t)(target - S->steps_done);
+    if (todo <= 0) return APIC_OK;
+    apic_status rc = f64 ? sim_run<double>(S, st, todo, use_graph)
+                         : sim_run<float>(S, st, todo, use_graph);
+    TRY(rc);
+    SimDev d;
+    TRY(sim_read_dev(S, st, &d));
+    if (S->prof.on) S->prof.collect();
+    S->steps_done = d.steps_done;
+    if (d.sticky == 0) return APIC_OK;
+    if (d.sticky & ~(kErrResize | kErrCapacity)) return status_from_err(d.sticky);
+    // grow: clear the sticky error, re-measure from the current state, retry
+    launch_clear_sticky(S->dev, st);
+    TRY(f64 ? sim_plan<double>(S, st, S->headroom * 1.5) : sim_plan<float>(S, st, S->headroom * 1.5));
+    S->headroom *= 1.5;
+    S->resizes += 1;
+  }
+  return APIC_E_DEVICE;
 }
 
 // ---------------------------------------------------------------------------
@@ -353,7 +588,7 @@ apic_status apic_create(apic_ctx **out, int device, size_t hbm_budget_bytes) {
   c->device = device;
   c->ws.budget = hbm_budget_bytes;
   c->cus = prop.multiProcessorCount;
-  c->persistent_wg = std::max(1, prop.multiProcessorCount) * 8;
+  c->persistent_wg = std::max(1, prop.multiProcessorCount) * 16;
   *out = c;
   return APIC_OK;
 }
@@ -423,16 +658,28 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
   if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
   if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
-  LayoutResult L;
+  Workspace &W = ctx->ws;
+  Plan P;
+  TRY(plan_tables(ctx, W, P, scenes, n_scenes, n_total, prec, nullptr, st));
+  if (n_total == 0) return APIC_OK;
   if (prec == APIC_FP64)
-    TRY(layout_phase<double>(ctx, st, scenes, n_scenes, n_total, (const double *)x, body_id, &L));
+    enqueue_prefix<double>(P, st, (const double *)x, body_id, nullptr, false);
   else
-    TRY(layout_phase<float>(ctx, st, scenes, n_scenes, n_total, (const float *)x, body_id, &L));
-  if (n_total > 0) {
-    HIPOK(hipMemcpyAsync(keys_sorted, L.keys, sizeof(uint32_t) * n_total,
-                         hipMemcpyDeviceToDevice, st));
-    HIPOK(hipMemcpyAsync(perm, L.perm, sizeof(uint32_t) * n_total, hipMemcpyDeviceToDevice, st));
-  }
+    enqueue_prefix<float>(P, st, (const float *)x, body_id, nullptr, false);
+  Counters c;
+  TRY(ctx->host_stage(sizeof(Counters)));
+  HIPOK(hipMemcpyAsync(ctx->stage, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  std::memcpy(&c, ctx->stage, sizeof(Counters));
+  TRY(status_from_err(c.err));
+  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0));
+  if (prec == APIC_FP64)
+    enqueue_sort<double>(P, st, (const double *)x, body_id, nullptr);
+  else
+    enqueue_sort<float>(P, st, (const float *)x, body_id, nullptr);
+  HIPOK(hipMemcpyAsync(keys_sorted, P.keys, sizeof(uint32_t) * n_total, hipMemcpyDeviceToDevice,
+                       st));
+  HIPOK(hipMemcpyAsync(perm, P.perm, sizeof(uint32_t) * n_total, hipMemcpyDeviceToDevice, st));
   HIPOK(hipStreamSynchronize(st));
   return APIC_OK;
 }
@@ -440,12 +687,177 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
 int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec) {
   if (n < 0) return -1;
   const int64_t tb = prec == APIC_FP64 ? 8 : 4;
-  if (blocks_hint <= 0) blocks_hint = n / 16 + 64;  // about 1.3 node blocks per 64 particles x 8
-  // particle state (input copies, sorted copies, series, normals) + sort + tables
-  int64_t per_particle = tb * (3 + 12 + 1 + 3 + 12 + 3 + 12 + 3) + 4 * 8 + sizeof(Segment) +
-                         sizeof(Item) * 2;
+  if (blocks_hint <= 0) blocks_hint = n / 16 + 64;
+  // resident state x2 (x, vC, m, body, orig), sorted scratch (t, m, normals,
+  // series), keys/values x2, segment/item tables; grid mass, 2 momentum
+  // buffers and per-body mass per node block.
+  int64_t per_particle = 2 * (tb * 16 + 2 + 4) + tb * (3 + 1 + 3 + 12) + 4 * 5 + 16 +
+                         (int64_t)sizeof(Segment) + 2 * (int64_t)sizeof(Item);
   int64_t per_block = kNodesPerBlock * (tb * 7 + 8) + 8 * 2;
   return n * per_particle + blocks_hint * per_block + (1 << 20);
+}
+
+apic_status apic_sim_create(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                            int32_t n_scenes, int64_t n_total, const double *dt, const void *x,
+                            const void *v, const void *C, const void *m, const uint16_t *body_id,
+                            apic_precision prec, apic_sim **out) {
+  if (!ctx || !out || !dt) return APIC_E_INVALID;
+  *out = nullptr;
+  TRY(validate_scenes(scenes, n_scenes, n_total));
+  if (n_total < 1 || !x || !v || !C || !m || !body_id) return APIC_E_INVALID;
+  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
+  for (int s = 0; s < n_scenes; ++s)
+    if (!std::isfinite(dt[s])) return APIC_E_INVALID;
+  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  apic_sim *S = new apic_sim();
+  S->ctx = ctx;
+  S->ws.budget = ctx->ws.budget;
+  S->n_scenes = n_scenes;
+  auto fail = [&](apic_status rc) {
+    apic_sim_destroy(S);
+    return rc;
+  };
+  apic_status rc = plan_tables(ctx, S->ws, S->plan, scenes, n_scenes, n_total, prec, dt, st);
+  if (rc) return fail(rc);
+  const size_t T = S->plan.tbytes;
+  const int64_t n = n_total;
+  for (int p = 0; p < 2; ++p) {
+    SimState &A = S->state[p];
+    if (hipMalloc(&A.x, T * 3 * n) != hipSuccess || hipMalloc(&A.vc, T * 12 * n) != hipSuccess ||
+        hipMalloc(&A.m, T * n) != hipSuccess ||
+        hipMalloc((void **)&A.body, sizeof(uint16_t) * n) != hipSuccess ||
+        hipMalloc((void **)&A.orig, sizeof(uint32_t) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(APIC_E_NOMEM);
+    }
+  }
+  if (hipMalloc((void **)&S->dev, sizeof(SimDev)) != hipSuccess ||
+      hipMalloc((void **)&S->drift, sizeof(double) * 2 * n_scenes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(APIC_E_NOMEM);
+  }
+  SimState &A = S->state[0];
+  if (hipMemcpyAsync(A.x, x, T * 3 * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(A.vc, v, T * 3 * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync((char *)A.vc + T * 3 * n, C, T * 9 * n, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(A.m, m, T * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(A.body, body_id, sizeof(uint16_t) * n, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return fail(APIC_E_DEVICE);
+  }
+  launch_iota(A.orig, n, st);
+  fill_bytes_zero(S->dev, sizeof(SimDev), st);
+  fill_bytes_zero(S->drift, sizeof(double) * 2 * n_scenes, st);
+  if (hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(APIC_E_DEVICE);
+  }
+  rc = prec == APIC_FP64 ? sim_plan<double>(S, st, S->headroom) : sim_plan<float>(S, st, S->headroom);
+  if (rc) return fail(rc);
+  *out = S;
+  return APIC_OK;
+}
+
+apic_status apic_sim_step(apic_sim *S, void *stream, int32_t n_steps, int32_t use_graph) {
+  if (!S || n_steps < 0) return APIC_E_INVALID;
+  if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  return sim_step_impl(S, (hipStream_t)stream, n_steps, use_graph);
+}
+
+apic_status apic_sim_read(apic_sim *S, void *stream, void *x, void *v, void *C) {
+  if (!S) return APIC_E_INVALID;
+  if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  const SimState &A = S->state[S->parity];
+  const int64_t n = S->plan.n;
+  if (S->plan.prec == APIC_FP64)
+    launch_unpermute<double>(A.orig, n, (const double *)A.x, (const double *)A.vc, (double *)x,
+                             (double *)v, (double *)C, st);
+  else
+    launch_unpermute<float>(A.orig, n, (const float *)A.x, (const float *)A.vc, (float *)x,
+                            (float *)v, (float *)C, st);
+  HIPOK(hipStreamSynchronize(st));
+  return APIC_OK;
+}
+
+apic_status apic_sim_report(apic_sim *S, apic_report *per_scene, double *max_drift,
+                            int64_t *steps_done) {
+  if (!S) return APIC_E_INVALID;
+  if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  const int ns = S->n_scenes;
+  const size_t rbytes = sizeof(double) * kRed * 2 * ns;
+  TRY(S->ctx->host_stage(rbytes + sizeof(Counters) + sizeof(double) * 2 * ns));
+  char *stg = (char *)S->ctx->stage;
+  HIPOK(hipMemcpy(stg, S->plan.red, rbytes, hipMemcpyDeviceToHost));
+  HIPOK(hipMemcpy(stg + rbytes, S->plan.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+  HIPOK(hipMemcpy(stg + rbytes + sizeof(Counters), S->drift, sizeof(double) * 2 * ns,
+                  hipMemcpyDeviceToHost));
+  Counters c;
+  std::memcpy(&c, stg + rbytes, sizeof(Counters));
+  if (per_scene) fill_report((const double *)stg, ns, c, per_scene);
+  if (max_drift) std::memcpy(max_drift, stg + rbytes + sizeof(Counters), sizeof(double) * 2 * ns);
+  if (steps_done) *steps_done = S->steps_done;
+  return APIC_OK;
+}
+
+apic_status apic_sim_set_profiling(apic_sim *S, int32_t enable) {
+  if (!S) return APIC_E_INVALID;
+  if (!enable) S->prof.collect();
+  S->prof.on = enable != 0;
+  return APIC_OK;
+}
+
+apic_status apic_sim_kernel_times(apic_sim *S, double *ms, int64_t *launches) {
+  if (!S) return APIC_E_INVALID;
+  S->prof.collect();
+  for (int k = 0; k < APIC_KC_COUNT; ++k) {
+    if (ms) ms[k] = S->prof.total_ms[k];
+    if (launches) launches[k] = S->prof.launches[k];
+    S->prof.total_ms[k] = 0.0;
+    S->prof.launches[k] = 0;
+  }
+  return APIC_OK;
+}
+
+apic_status apic_sim_info(apic_sim *S, int64_t *out) {
+  if (!S || !out) return APIC_E_INVALID;
+  if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  Counters c;
+  HIPOK(hipMemcpy(&c, S->plan.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+  out[0] = S->plan.n;
+  out[1] = c.n_sblocks;
+  out[2] = c.n_bblocks;
+  out[3] = c.n_seg;
+  out[4] = c.n_items;
+  out[5] = S->plan.sort_bits;
+  size_t held = S->ws.held;
+  held += 2 * (size_t)S->plan.n * (S->plan.tbytes * 16 + 6);
+  out[6] = (int64_t)held;
+  return APIC_OK;
+}
+
+void apic_sim_destroy(apic_sim *S) {
+  if (!S) return;
+  (void)hipSetDevice(S->ctx->device);
+  (void)hipDeviceSynchronize();
+  for (int p = 0; p < 2; ++p) {
+    if (S->exec[p]) (void)hipGraphExecDestroy(S->exec[p]);
+    SimState &A = S->state[p];
+    if (A.x) (void)hipFree(A.x);
+    if (A.vc) (void)hipFree(A.vc);
+    if (A.m) (void)hipFree(A.m);
+    if (A.body) (void)hipFree(A.body);
+    if (A.orig) (void)hipFree(A.orig);
+  }
+  if (S->dev) (void)hipFree(S->dev);
+  if (S->drift) (void)hipFree(S->drift);
+  if (S->capture_stream) (void)hipStreamDestroy(S->capture_stream);
+  S->prof.release();
+  S->ws.release();
+  delete S;
 }
 
 }  // extern "C"

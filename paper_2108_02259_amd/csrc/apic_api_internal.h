@@ -1,17 +1,21 @@
-// apic_api_internal.h -- the context object behind the C ABI.
+// apic_api_internal.h -- the context, plan and resident-driver objects behind
+// the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "apic_contact.h"
 #include "apic_internal.h"
+#include "kernels.h"
 
 namespace apic {
 
 enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
-  kValsB, kHist, kPartial, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp, kFlags,
-  kItems, kSmap, kBmap, kGMass, kGBuf0, kGBuf1, kBMass, kNumBufs
+  kValsB, kHist, kPartial, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
+  kFlags, kItems, kSmap, kBmap, kGMass, kGBuf0, kGBuf1, kBMass, kBoxRec, kRecGather, kRecItems, kNumBufs
 };
 
 // Grow-only device buffers, bounded by an HBM budget.
@@ -24,15 +28,86 @@ struct Workspace {
   void release();
 };
 
-struct LayoutResult {
+// Capacities and device pointers of one step.  Everything a step enqueues is
+// fixed by the plan, so a step can be captured into a graph and replayed.
+struct Plan {
+  apic_precision prec = APIC_FP32_MIXED;
+  int tbytes = 4;
+  int64_t n = 0;
+  int ns = 0;
   int64_t nb_cap = 0;
-  int32_t max_iter = 0;
-  int32_t key_blocks = 0;
-  int64_t smap_total = 0, bmap_total = 0;
-  int sort_bits = 0;
-  uint32_t *keys = nullptr;  // sorted keys
-  uint32_t *perm = nullptr;  // sorted position -> input index
+  int max_iter = 0;
+  int sort_bits = 32;
+  int64_t seg_cap = 0, item_cap = 0, smap_cap = 0, bmap_cap = 0, sblk_cap = 0, bblk_cap = 0;
+  int grid_wg = 1;
+  bool ready = false;
+  SceneDev *sc = nullptr;
+  SceneAcc *sacc = nullptr;
+  SceneLay *slay = nullptr;
+  BodyAcc *bacc = nullptr;
+  BodyLay *blay = nullptr;
+  Counters *cnt = nullptr;
+  int64_t *tot = nullptr;
+  double *red = nullptr;
+  BoxRec *box_rec = nullptr;
+  RedRec *rec_gather = nullptr, *rec_items = nullptr;
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr;
+  int32_t *partial = nullptr;
+  uint32_t *keys = nullptr, *perm = nullptr;
+  void *t = nullptr, *ms = nullptr, *nrm = nullptr, *Y = nullptr;
+  int32_t *sbody = nullptr;
+  Segment *seg = nullptr;
+  int32_t *segtmp = nullptr, *flags = nullptr;
+  Item *items = nullptr;
+  int32_t *smap = nullptr, *bmap = nullptr;
+  GridPtrs g = {};
 };
+
+// Kernel timing of eager steps: every launch between begin() and end(kind)
+// gets its own event pair (recorded with the dispatch); end() files them
+// under `kind`.
+struct Profiler : LaunchTimer {
+  struct Rec {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> free_events;
+  std::vector<Rec> recs;
+  size_t open_from = 0;  // first record of the current class
+  double total_ms[APIC_KC_COUNT] = {};
+  int64_t launches[APIC_KC_COUNT] = {};
+  void events(hipEvent_t *start, hipEvent_t *stop) override;
+  void begin(hipStream_t st);
+  void end(int kind, hipStream_t st);
+  void collect();
+  void release();
+};
+
+// Resident particle state in sorted order (x, v|C as 12 rows, m, body, and the
+// caller index of each particle).
+struct SimState {
+  void *x = nullptr, *vc = nullptr, *m = nullptr;
+  uint16_t *body = nullptr;
+  uint32_t *orig = nullptr;
+};
+
+// Device-side driver status.
+struct SimDev {
+  int32_t sticky;      // error bits of any step since the last clear
+  int32_t pad;
+  int64_t steps_done;  // completed steps
+};
+
+// ---- driver kernels (misc.hip) --------------------------------------------
+void launch_copy_sticky(Counters *cnt, const int32_t *sticky, hipStream_t st);
+void launch_clear_sticky(SimDev *dev, hipStream_t st);
+void launch_step_end(const Counters *cnt, const double *red, int ns, SimDev *dev, double *drift,
+                     hipStream_t st);
+void launch_iota(uint32_t *p, int64_t n, hipStream_t st);
+template <typename T>
+void launch_unpermute(const uint32_t *orig, int64_t n, const T *x_sorted, const T *vc_sorted,
+                      T *x_out, T *v_out, T *C_out, hipStream_t st);
 
 }  // namespace apic
 
@@ -43,8 +118,25 @@ struct apic_ctx {
   apic::Workspace ws;
   void *stage = nullptr;  // pinned host staging
   size_t stage_bytes = 0;
-  int64_t last_sblocks = 0;
   apic_status host_stage(size_t bytes);
+};
+
+struct apic_sim {
+  apic_ctx *ctx = nullptr;
+  apic::Workspace ws;
+  apic::Plan plan;
+  apic::SimState state[2];
+  int parity = 0;            // state[parity] holds the current state
+  int n_scenes = 0;
+  apic::SimDev *dev = nullptr;
+  double *drift = nullptr;   // per scene: max |dP|/P_scale, max |dL|/L_scale
+  int64_t steps_done = 0;
+  double headroom = 1.5;
+  int resizes = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool graph_ok = false;
+  apic::Profiler prof;
 };
 
 apic_status validate_scenes(const apic_scene *scenes, int32_t ns, int64_t n_total);

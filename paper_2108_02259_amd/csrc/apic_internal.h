@@ -2,12 +2,22 @@
 // contact library.  Nothing here is part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "apic_contact.h"
 
 namespace apic {
+
+// Optional timing of every launch: when a timer is installed (eager profiled
+// steps), kernels are launched with HIP's extended launch, which records a
+// start/stop event pair with the dispatch itself on the launch stream.
+struct LaunchTimer {
+  virtual void events(hipEvent_t *start, hipEvent_t *stop) = 0;
+  virtual ~LaunchTimer() = default;
+};
+extern thread_local LaunchTimer *g_launch_timer;
 
 // ---------------------------------------------------------------------------
 // Layout constants
@@ -34,6 +44,7 @@ enum : int32_t {
   kErrCapacity = 4,
   kErrBody = 8,
   kErrNonFinite = 16,
+  kErrResize = 32,      // key space or map exceeded a resident plan's capacity
 };
 
 // ---------------------------------------------------------------------------
@@ -43,6 +54,7 @@ struct SceneDev {
   double origin[3];
   double h;
   double mu;
+  double dt;             // drift step of the resident driver (0 in a single call)
   int64_t offset, count;
   int32_t dims[3];
   int32_t n_iter;
@@ -107,6 +119,34 @@ struct Counters {
 // Per-scene FP64 reductions: P(3) L(3) E Pscale Lscale count uncon.
 constexpr int kRed = 11;
 
+// Partial results of one wavefront (or work item), reduced by a second kernel
+// instead of many same-address atomics (those serialise at ~10 ns each).
+struct RedRec {
+  int32_t key;  // scene, or -1 if empty
+  int32_t pad;
+  double v[kRed];
+};
+
+struct BoxRec {
+  int32_t key;  // capacity body index, or -1 if empty
+  int32_t mn[3];
+  int32_t mx[3];
+  int32_t pad;
+};
+
+// Compiler memory barrier: keeps the LDS read-add-write of one stencil node
+// ahead of the next node's (LDS instructions of a wave complete in order).
+#define LDS_ORDER() asm volatile("" ::: "memory")
+
+// Pin a value at this point of the instruction stream (and order memory
+// around it): arithmetic producing it cannot sink below, arithmetic using it
+// cannot rise above.  Keeps the unrolled stencil loops from holding all 64
+// nodes' operands in registers at once.
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+  asm volatile("" : "+v"(v) : : "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Small device helpers
 // ---------------------------------------------------------------------------
@@ -135,3 +175,15 @@ __device__ __forceinline__ int scene_of(const SceneDev *sc, int ns, int64_t p) {
 }
 
 }  // namespace apic
+
+#define APIC_LAUNCH(kernel, grid, block, shmem, stream, ...)                              \
+  do {                                                                                    \
+    if (apic::g_launch_timer) {                                                           \
+      hipEvent_t start_, stop_;                                                           \
+      apic::g_launch_timer->events(&start_, &stop_);                                      \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, start_, stop_, 0,         \
+                            __VA_ARGS__);                                                 \
+    } else {                                                                              \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                \
+    }                                                                                     \
+  } while (0)

@@ -41,13 +41,18 @@ int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n
                uint32_t *hist, int32_t *partial, int64_t *total, hipStream_t st);
 
 // ---- layout (layout.hip) ---------------------------------------------------
+// One box record per wavefront (rec has ceil(n/256)*4 entries), then reduced.
 template <typename T>
 void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                  SceneAcc *sacc, BodyAcc *bacc, Counters *cnt, hipStream_t st);
+                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, hipStream_t st);
+inline int64_t wave_records(int64_t n) { return (n + 255) / 256 * 4; }
 void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
                         hipStream_t st);
-void launch_domains(const SceneDev *sc, int ns, const SceneAcc *sacc, const BodyAcc *bacc,
-                    SceneLay *slay, BodyLay *blay, Counters *cnt, hipStream_t st);
+// key_bits > 0: flag kErrResize if the key space needs more bits; smap_cap /
+// bmap_cap > 0: flag kErrResize if the node-block maps need more entries.
+void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, const BodyAcc *bacc,
+                    SceneLay *slay, BodyLay *blay, Counters *cnt, int key_bits, int64_t smap_cap,
+                    int64_t bmap_cap, hipStream_t st);
 template <typename T>
 void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
                  const BodyLay *blay, uint32_t *keys, hipStream_t st);
@@ -55,7 +60,8 @@ template <typename T>
 void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
                    const T *m, const uint16_t *body, const SceneDev *sc, int ns,
                    T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
-                   T *x_out, uint16_t *body_out, double *red, hipStream_t st);
+                   T *x_out, uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
+                   RedRec *rec, double *direct, hipStream_t st);
 void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay,
                      Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,
@@ -83,20 +89,33 @@ struct StepArgs {
 };
 
 template <typename T>
+void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStream_t st);
+template <typename T>
+void launch_normals(const StepArgs &a, const T *t, T *nrm, GridPtrs g, hipStream_t st);
+template <typename T>
 void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
                  hipStream_t st);
 template <typename T>
 void launch_gridvel(const StepArgs &a, GridPtrs g, int cur, hipStream_t st);
 // One fused round k >= 1: G2P of buffer `cur`, the rule, P2G of the next
-// series field into buffer 1-cur.  Scenes whose n_iter == k-1 finish here.
+// series field into buffer 1-cur.  Scenes whose n_iter == k-1 finish here
+// (writing Vhat to v_out/C_out at perm[i], or at i when perm is null).
+// `final` selects the finishing-only kernel (k = max n_iter + 1).
 template <typename T>
-void launch_iter(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, T *nrm, T *Y,
-                 GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out, T *x_io,
-                 double dt, double *red, hipStream_t st);
-// Final G2P (k = max n_iter + 1): Vhat = Vbar + D for the remaining scenes.
+void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
+                 const T *nrm, T *Y, GridPtrs g, int cur, const uint32_t *perm, T *v_out,
+                 T *C_out, hipStream_t st);
+// FP64 momentum after the step (+ the resident driver's drift).
 template <typename T>
-void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *Y,
-                  GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out, T *x_io,
-                  double dt, double *red, hipStream_t st);
+void launch_after(int64_t n, const uint32_t *perm, T *x, const T *v, const T *C,
+                  const T *m_sorted, const T *nrm, const int32_t *sbody, const BodyLay *blay,
+                  const SceneDev *sc, const Counters *cnt, int apply_drift, RedRec *rec,
+                  double *direct, hipStream_t st);
+// Reduce records [0, count) (count = *count_dev if non-null, skipped when the
+// step has an error) into out[key * kRed + c].
+void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *count_dev,
+                       const Counters *cnt, double *out, hipStream_t st);
+// Reduce box records into the per-body boxes.
+void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, hipStream_t st);
 
 }  // namespace apic

@@ -54,39 +54,6 @@ __device__ __forceinline__ void wave_minmax3(int32_t mn[3], int32_t mx[3]) {
     }
 }
 
-// Box update for the key `id` of each lane: one set of atomics per wave when
-// the wave is uniform in `id`, otherwise per lane.
-__device__ __forceinline__ void box_update(bool ok, int id, const int32_t B[3], int32_t *bmin,
-                                           int32_t *bmax, int stride) {
-  const int lane = threadIdx.x & 63;
-  uint64_t valid = __ballot(ok);
-  if (valid == 0) return;
-  int first = __ffsll((unsigned long long)valid) - 1;
-  int id0 = __shfl(id, first, 64);
-  bool uniform = __ballot(ok && id != id0) == 0;
-  if (uniform) {
-    int32_t mn[3], mx[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = ok ? B[d] : INT_MAX;
-      mx[d] = ok ? B[d] : INT_MIN;
-    }
-    wave_minmax3(mn, mx);
-    if (lane == first)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        atomicMin(&bmin[(int64_t)id0 * stride + d], mn[d]);
-        atomicMax(&bmax[(int64_t)id0 * stride + d], mx[d]);
-      }
-  } else if (ok) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      atomicMin(&bmin[(int64_t)id * stride + d], B[d]);
-      atomicMax(&bmax[(int64_t)id * stride + d], B[d]);
-    }
-  }
-}
-
 __global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ns) {
@@ -111,23 +78,28 @@ void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Count
                         hipStream_t st) {
   int64_t m = ns > nb_cap ? ns : nb_cap;
   if (m < 1) m = 1;
-  k_layout_init<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(sacc, ns, bacc, nb_cap, cnt);
+  APIC_LAUNCH(k_layout_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, sacc, ns, bacc, nb_cap, cnt);
 }
 
+// Cells of every particle; each wavefront emits one record with the block box
+// of its body (if all its valid lanes share one body), else falls back to
+// per-lane atomics.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body, int64_t n,
-                                               const SceneDev *sc, int ns, SceneAcc *sacc,
-                                               BodyAcc *bacc, Counters *cnt) {
+                                               const SceneDev *sc, int ns, BodyAcc *bacc,
+                                               BoxRec *rec, Counters *cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = p >> 6;
   bool ok = p < n;
-  int s = 0, gb = 0, err = 0, b = 0;
+  int gb = 0, err = 0;
   int32_t B[3] = {0, 0, 0};
   if (ok) {
-    s = scene_of(sc, ns, p);
+    const int s = scene_of(sc, ns, p);
     const SceneDev sd = sc[s];
     CellInfo ci = cell_of(x, n, p, sd);
     err |= ci.err;
-    b = body[p];
+    const int b = body[p];
     if (b >= sd.n_bodies) {
       err |= kErrBody;
       ci.ok = false;
@@ -138,135 +110,230 @@ __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body,
     for (int d = 0; d < 3; ++d) B[d] = floor_div4(ci.c[d]);
   }
   if (err) atomicOr(&cnt->err, err);
-  box_update(ok, gb, B, &bacc[0].bmin[0], &bacc[0].bmax[0], 6);
-  box_update(ok, s, B, &sacc[0].bmin[0], &sacc[0].bmax[0], 8);
-  // max body id per scene
-  uint64_t valid = __ballot(ok);
+  const uint64_t valid = __ballot(ok);
+  BoxRec r;
+  r.key = -1;
+  r.pad = 0;
   if (valid) {
-    int first = __ffsll((unsigned long long)valid) - 1;
-    int s0 = __shfl(s, first, 64);
-    bool uniform = __ballot(ok && s != s0) == 0;
-    int mb = ok ? b : -1;
+    const int first = __ffsll((unsigned long long)valid) - 1;
+    const int gb0 = __shfl(gb, first, 64);
+    const bool uniform = __ballot(ok && gb != gb0) == 0;
     if (uniform) {
+      int32_t mn[3], mx[3];
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) mb = max(mb, __shfl_xor(mb, o, 64));
-      if ((int)(threadIdx.x & 63) == first) atomicMax(&sacc[s0].max_body, mb);
+      for (int d = 0; d < 3; ++d) {
+        mn[d] = ok ? B[d] : INT_MAX;
+        mx[d] = ok ? B[d] : INT_MIN;
+      }
+      wave_minmax3(mn, mx);
+      r.key = gb0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        r.mn[d] = mn[d];
+        r.mx[d] = mx[d];
+      }
     } else if (ok) {
-      atomicMax(&sacc[s].max_body, b);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&bacc[gb].bmin[d], B[d]);
+        atomicMax(&bacc[gb].bmax[d], B[d]);
+      }
     }
   }
+  if (lane == 0) rec[wave] = r;
 }
 
 template <typename T>
 void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                  SceneAcc *sacc, BodyAcc *bacc, Counters *cnt, hipStream_t st) {
+                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, hipStream_t st) {
   if (n <= 0) return;
-  k_cells<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x, body, n, sc, ns, sacc, bacc, cnt);
+  APIC_LAUNCH((k_cells<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, body, n, sc, ns, bacc, rec, cnt);
+}
+
+// Block-wide reduction of 256 box records: one set of atomics per block when
+// all its records name one body, per record otherwise.
+__global__ __launch_bounds__(256) void k_reduce_box(const BoxRec *rec, int64_t count,
+                                                    BodyAcc *bacc) {
+  __shared__ int32_t smn[3][4], smx[3][4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  BoxRec r;
+  r.key = -1;
+  if (i < count) r = rec[i];
+  __shared__ int32_t key0;
+  if (threadIdx.x == 0) key0 = -2;
+  __syncthreads();
+  if (r.key >= 0) atomicCAS(&key0, -2, r.key);
+  __syncthreads();
+  const int k0 = key0;
+  const bool uniform = __syncthreads_and(r.key < 0 || r.key == k0);
+  if (k0 < 0) return;  // no valid record in this block
+  if (uniform) {
+    int32_t mn[3], mx[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = r.key >= 0 ? r.mn[d] : INT_MAX;
+      mx[d] = r.key >= 0 ? r.mx[d] : INT_MIN;
+    }
+    wave_minmax3(mn, mx);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+      for (int d = 0; d < 3; ++d) {
+        smn[d][wave] = mn[d];
+        smx[d][wave] = mx[d];
+      }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int d = 0; d < 3; ++d) {
+        int32_t a = smn[d][0], b = smx[d][0];
+        for (int w = 1; w < 4; ++w) {
+          a = min(a, smn[d][w]);
+          b = max(b, smx[d][w]);
+        }
+        atomicMin(&bacc[k0].bmin[d], a);
+        atomicMax(&bacc[k0].bmax[d], b);
+      }
+  } else if (r.key >= 0) {
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&bacc[r.key].bmin[d], r.mn[d]);
+      atomicMax(&bacc[r.key].bmax[d], r.mx[d]);
+    }
+  }
+}
+
+void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, hipStream_t st) {
+  if (count <= 0) return;
+  APIC_LAUNCH(k_reduce_box, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, rec, count, bacc);
 }
 
 // ---------------------------------------------------------------------------
 // domains: body key offsets and node-block maps (one workgroup)
 // ---------------------------------------------------------------------------
+// Exclusive scan of one int64 per thread across the 1024-thread block.
 __device__ __forceinline__ int64_t block_excl_scan64(int64_t x, int64_t *lds, int64_t *total) {
-  // 1024 threads, simple two-level scan through LDS
-  const int tid = threadIdx.x;
-  lds[tid] = x;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int64_t y = tid >= o ? lds[tid - o] : 0;
-    __syncthreads();
-    lds[tid] += y;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
   }
-  int64_t inc = lds[tid];
-  *total = lds[1023];
+  if (lane == 63) lds[wave] = inc;
   __syncthreads();
-  return inc - x;
+  int64_t woff = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    int64_t v = lds[w];
+    if (w < wave) woff += v;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return woff + inc - x;
 }
 
-__global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, const SceneAcc *sacc,
-                                                  const BodyAcc *bacc, SceneLay *slay,
-                                                  BodyLay *blay, Counters *cnt) {
-  __shared__ int64_t lds[1024];
+__device__ __forceinline__ int scene_of_body(const SceneDev *sc, int ns, int gb) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sc[mid].body_base <= gb) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bodies in capacity order (scene-major, so empty bodies take no key space):
+// key and body-map offsets by a block scan; scene boxes as the union of their
+// bodies' boxes; then scene-map offsets.
+__global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, int nb_cap,
+                                                  SceneAcc *sacc, const BodyAcc *bacc,
+                                                  SceneLay *slay, BodyLay *blay, Counters *cnt,
+                                                  int key_bits, int64_t smap_cap,
+                                                  int64_t bmap_cap) {
+  __shared__ int64_t lds[16];
   int64_t carry_key = 0, carry_bmap = 0, carry_smap = 0;
-  for (int base = 0; base < ns; base += 1024) {
-    const int s = base + threadIdx.x;
-    int64_t key_sum = 0, bmap_sum = 0, smap_vol = 0;
-    if (s < ns) {
-      const SceneAcc a = sacc[s];
-      if (a.bmin[0] <= a.bmax[0]) {
-        smap_vol = 1;
-        for (int d = 0; d < 3; ++d) smap_vol *= (int64_t)(a.bmax[d] - a.bmin[d] + 2);
-      }
-      for (int b = 0; b <= a.max_body; ++b) {
-        const BodyAcc ba = bacc[sc[s].body_base + b];
-        if (ba.bmin[0] > ba.bmax[0]) continue;
-        int64_t kv = 1, mv = 1;
+  for (int base = 0; base < nb_cap; base += 1024) {
+    const int gb = base + threadIdx.x;
+    int64_t kv = 0, mv = 0;
+    BodyAcc ba;
+    bool ne = false;
+    if (gb < nb_cap) {
+      ba = bacc[gb];
+      ne = ba.bmin[0] <= ba.bmax[0];
+      if (ne) {
+        kv = 1;
+        mv = 1;
         for (int d = 0; d < 3; ++d) {
           int64_t e = (int64_t)(ba.bmax[d] - ba.bmin[d] + 1);
           kv *= e;
           mv *= e + 1;
         }
-        key_sum += kv;
-        bmap_sum += mv;
       }
     }
-    int64_t tk, tb, ts;
-    int64_t ok_ = block_excl_scan64(key_sum, lds, &tk) + carry_key;
-    int64_t ob_ = block_excl_scan64(bmap_sum, lds, &tb) + carry_bmap;
-    int64_t os_ = block_excl_scan64(smap_vol, lds, &ts) + carry_smap;
-    if (s < ns) {
-      const SceneAcc a = sacc[s];
-      SceneLay L;
-      L.smap_off = os_;
+    int64_t tk, tb;
+    const int64_t koff = block_excl_scan64(kv, lds, &tk) + carry_key;
+    const int64_t boff = block_excl_scan64(mv, lds, &tb) + carry_bmap;
+    if (gb < nb_cap) {
+      const int s = scene_of_body(sc, ns, gb);
+      BodyLay bl;
+      bl.scene = s;
+      bl.key_off = (int32_t)(koff < kMaxKeyBlocks ? koff : kMaxKeyBlocks);
+      bl.bmap_off = boff;
       for (int d = 0; d < 3; ++d) {
-        bool ne = a.bmin[0] <= a.bmax[0];
+        bl.bmin[d] = ne ? ba.bmin[d] : 0;
+        bl.ext[d] = ne ? ba.bmax[d] - ba.bmin[d] + 1 : 0;
+      }
+      blay[gb] = bl;
+      if (ne)
+        for (int d = 0; d < 3; ++d) {
+          atomicMin(&sacc[s].bmin[d], ba.bmin[d]);
+          atomicMax(&sacc[s].bmax[d], ba.bmax[d]);
+        }
+    }
+    carry_key += tk;
+    carry_bmap += tb;
+  }
+  __syncthreads();
+  for (int base = 0; base < ns; base += 1024) {
+    const int s = base + threadIdx.x;
+    int64_t vol = 0;
+    SceneAcc a;
+    if (s < ns) {
+      a = sacc[s];
+      if (a.bmin[0] <= a.bmax[0]) {
+        vol = 1;
+        for (int d = 0; d < 3; ++d) vol *= (int64_t)(a.bmax[d] - a.bmin[d] + 2);
+      }
+    }
+    int64_t ts;
+    const int64_t soff = block_excl_scan64(vol, lds, &ts) + carry_smap;
+    if (s < ns) {
+      SceneLay L;
+      L.smap_off = soff;
+      const bool ne = a.bmin[0] <= a.bmax[0];
+      for (int d = 0; d < 3; ++d) {
         L.smin[d] = ne ? a.bmin[d] : 0;
         L.sext[d] = ne ? a.bmax[d] - a.bmin[d] + 2 : 0;
       }
       slay[s] = L;
-      int64_t kcur = ok_, bcur = ob_;
-      for (int b = 0; b <= a.max_body; ++b) {
-        const int gb = sc[s].body_base + b;
-        const BodyAcc ba = bacc[gb];
-        BodyLay bl;
-        bl.scene = s;
-        bl.key_off = (int32_t)(kcur < kMaxKeyBlocks ? kcur : kMaxKeyBlocks);
-        bl.bmap_off = bcur;
-        if (ba.bmin[0] > ba.bmax[0]) {
-          for (int d = 0; d < 3; ++d) {
-            bl.bmin[d] = 0;
-            bl.ext[d] = 0;
-          }
-        } else {
-          int64_t kv = 1, mv = 1;
-          for (int d = 0; d < 3; ++d) {
-            bl.bmin[d] = ba.bmin[d];
-            bl.ext[d] = ba.bmax[d] - ba.bmin[d] + 1;
-            kv *= bl.ext[d];
-            mv *= bl.ext[d] + 1;
-          }
-          kcur += kv;
-          bcur += mv;
-        }
-        blay[gb] = bl;
-      }
     }
-    carry_key += tk;
-    carry_bmap += tb;
     carry_smap += ts;
   }
   if (threadIdx.x == 0) {
     if (carry_key > kMaxKeyBlocks) atomicOr(&cnt->err, kErrKeyOverflow);
+    if (key_bits > 0 && key_bits < 32 && carry_key * 64 > ((int64_t)1 << key_bits))
+      atomicOr(&cnt->err, kErrResize);
+    if ((smap_cap > 0 && carry_smap > smap_cap) || (bmap_cap > 0 && carry_bmap > bmap_cap))
+      atomicOr(&cnt->err, kErrResize);
     cnt->key_blocks = (int32_t)(carry_key < kMaxKeyBlocks ? carry_key : kMaxKeyBlocks);
     cnt->smap_total = carry_smap;
     cnt->bmap_total = carry_bmap;
   }
 }
 
-void launch_domains(const SceneDev *sc, int ns, const SceneAcc *sacc, const BodyAcc *bacc,
-                    SceneLay *slay, BodyLay *blay, Counters *cnt, hipStream_t st) {
-  k_domains<<<1, 1024, 0, st>>>(sc, ns, sacc, bacc, slay, blay, cnt);
+void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, const BodyAcc *bacc,
+                    SceneLay *slay, BodyLay *blay, Counters *cnt, int key_bits, int64_t smap_cap,
+                    int64_t bmap_cap, hipStream_t st) {
+  APIC_LAUNCH(k_domains, dim3(1), dim3(1024), 0, st, sc, ns, nb_cap, sacc, bacc, slay, blay, cnt, key_bits, smap_cap,
+                                bmap_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,7 +366,7 @@ template <typename T>
 void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
                  const BodyLay *blay, uint32_t *keys, hipStream_t st) {
   if (n <= 0) return;
-  k_keys<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x, body, n, sc, ns, blay, keys);
+  APIC_LAUNCH((k_keys<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, body, n, sc, ns, blay, keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,24 +378,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Accumulate kRed per-scene quantities (wave-aggregated when uniform).
-__device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed], double *red) {
+// One record per wavefront of per-scene sums (when the wave is uniform in
+// scene; per-lane atomics into `direct` otherwise).
+__device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed], RedRec *rec,
+                                             int64_t wave, double *direct) {
   const int lane = threadIdx.x & 63;
-  uint64_t valid = __ballot(ok);
-  if (valid == 0) return;
-  int first = __ffsll((unsigned long long)valid) - 1;
-  int s0 = __shfl(s, first, 64);
-  bool uniform = __ballot(ok && s != s0) == 0;
-  if (uniform) {
+  const uint64_t valid = __ballot(ok);
+  int key = -1;
+  if (valid) {
+    const int first = __ffsll((unsigned long long)valid) - 1;
+    const int s0 = __shfl(s, first, 64);
+    const bool uniform = __ballot(ok && s != s0) == 0;
+    if (uniform) {
+      key = s0;
 #pragma unroll
-    for (int k = 0; k < kRed; ++k) {
-      double v = wave_sum(ok ? q[k] : 0.0);
-      if (lane == first) atomicAdd(&red[(int64_t)s0 * kRed + k], v);
+      for (int k = 0; k < kRed; ++k) {
+        double v = wave_sum(ok ? q[k] : 0.0);
+        if (lane == 0) rec[wave].v[k] = v;
+      }
+    } else if (ok) {
+#pragma unroll
+      for (int k = 0; k < kRed; ++k) atomicAdd(&direct[(int64_t)s * kRed + k], q[k]);
     }
-  } else if (ok) {
-#pragma unroll
-    for (int k = 0; k < kRed; ++k) atomicAdd(&red[(int64_t)s * kRed + k], q[k]);
   }
+  if (lane == 0) rec[wave].key = key;
 }
 
 // P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
@@ -360,7 +433,8 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, int64_t n,
                                                 const uint16_t *body, const SceneDev *sc, int ns,
                                                 T *t_out, T *vbar_out, T *m_out,
                                                 int32_t *sbody_out, T *x_out, uint16_t *body_out,
-                                                double *red) {
+                                                const uint32_t *orig_in, uint32_t *orig_out,
+                                                RedRec *rec, double *direct) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n;
   int s = 0;
@@ -393,21 +467,80 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, int64_t n,
     const int b = body[p];
     sbody_out[i] = sd.body_base + (b < sd.n_bodies ? b : 0);
     if (body_out) body_out[i] = (uint16_t)b;
-    if (red) momentum_terms(r, vv, CC, (double)mv, sd.h, q);
+    if (orig_out) orig_out[i] = orig_in ? orig_in[p] : (uint32_t)p;
+    if (rec) momentum_terms(r, vv, CC, (double)mv, sd.h, q);
   }
-  if (red) reduce_scene(ok, s, q, red);
+  if (rec) reduce_scene(ok, s, q, rec, i >> 6, direct);
 }
 
 template <typename T>
 void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
                    const T *m, const uint16_t *body, const SceneDev *sc, int ns, T *t_out,
                    T *vbar_out, T *m_out, int32_t *sbody_out, T *x_out, uint16_t *body_out,
-                   double *red, hipStream_t st) {
+                   const uint32_t *orig_in, uint32_t *orig_out, RedRec *rec, double *direct,
+                   hipStream_t st) {
   if (n <= 0) return;
-  k_gather<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(perm, n, x, v, C, m, body, sc, ns,
+  APIC_LAUNCH((k_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n, x, v, C, m, body, sc, ns,
                                                             t_out, vbar_out, m_out, sbody_out,
-                                                            x_out, body_out, red);
+                                                            x_out, body_out, orig_in, orig_out,
+                                                            rec, direct);
 }
+
+// Momentum after the contact step (and the drift x += dt v of the resident
+// driver).  Sorted index i; the result lives at perm[i] (caller order) when
+// perm is given, else at i (resident sorted state).  The momentum uses the
+// positions before the drift.
+template <typename T>
+__global__ __launch_bounds__(256) void k_after(int64_t n, const uint32_t *perm, T *x, const T *v,
+                                               const T *C, const T *m_sorted, const T *nrm,
+                                               const int32_t *sbody, const BodyLay *blay,
+                                               const SceneDev *sc, const Counters *cnt,
+                                               int apply_drift, RedRec *rec, double *direct) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < n && cnt->err == 0;
+  int s = 0;
+  double q[kRed];
+  if (ok) {
+    const int64_t p = perm ? (int64_t)perm[i] : i;
+    s = blay[sbody[i]].scene;
+    const SceneDev &sd = sc[s];
+    double r[3], vv[3], CC[9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      vv[d] = (double)v[d * n + p];
+      r[d] = (double)x[d * n + p] - sd.origin[d];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) CC[k] = (double)C[k * n + p];
+    momentum_terms(r, vv, CC, (double)m_sorted[i], sd.h, q);
+    q[10] = (sd.n_iter > 0 && nrm && nrm[i] == T(0) && nrm[n + i] == T(0) && nrm[2 * n + i] == T(0))
+                ? 1.0 : 0.0;
+    if (apply_drift)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d * n + p] = x[d * n + p] + (T)(sd.dt * vv[d]);
+  }
+  reduce_scene(ok, s, q, rec, i >> 6, direct);
+}
+
+template <typename T>
+void launch_after(int64_t n, const uint32_t *perm, T *x, const T *v, const T *C,
+                  const T *m_sorted, const T *nrm, const int32_t *sbody, const BodyLay *blay,
+                  const SceneDev *sc, const Counters *cnt, int apply_drift, RedRec *rec,
+                  double *direct, hipStream_t st) {
+  if (n <= 0) return;
+  APIC_LAUNCH((k_after<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm, x, v, C, m_sorted, nrm, sbody,
+                                                           blay, sc, cnt, apply_drift, rec,
+                                                           direct);
+}
+
+template void launch_after<float>(int64_t, const uint32_t *, float *, const float *,
+                                  const float *, const float *, const float *, const int32_t *,
+                                  const BodyLay *, const SceneDev *, const Counters *, int,
+                                  RedRec *, double *, hipStream_t);
+template void launch_after<double>(int64_t, const uint32_t *, double *, const double *,
+                                   const double *, const double *, const double *,
+                                   const int32_t *, const BodyLay *, const SceneDev *,
+                                   const Counters *, int, RedRec *, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // segments and work items
@@ -506,14 +639,14 @@ void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *p
   if (n <= 0) return;
   unsigned g = (unsigned)((n + 255) / 256);
   if (g > 8192) g = 8192;
-  k_seg_flags<<<g, 256, 0, st>>>(keys, n, flags);
+  APIC_LAUNCH(k_seg_flags, dim3(g), dim3(256), 0, st, keys, n, flags);
   scan_exclusive(flags, flags, n, nullptr, &tot[0], partial, 0, st);
-  k_seg_heads<<<g, 256, 0, st>>>(keys, n, flags, sbody, blay, seg, seg_cap, cnt);
+  APIC_LAUNCH(k_seg_heads, dim3(g), dim3(256), 0, st, keys, n, flags, sbody, blay, seg, seg_cap, cnt);
   unsigned gs = (unsigned)((seg_cap + 255) / 256);
   if (gs > 8192) gs = 8192;
-  k_seg_counts<<<gs, 256, 0, st>>>(seg, seg_cap, &tot[0], n, seg_tmp, cnt);
+  APIC_LAUNCH(k_seg_counts, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], n, seg_tmp, cnt);
   scan_exclusive(seg_tmp, seg_tmp, seg_cap, &tot[0], &tot[1], partial, 0, st);
-  k_items<<<gs, 256, 0, st>>>(seg, seg_cap, &tot[0], seg_tmp, items, item_cap, cnt, &tot[1]);
+  APIC_LAUNCH(k_items, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], seg_tmp, items, item_cap, cnt, &tot[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,24 +720,67 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
                  int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
                  int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,
                  int64_t bblk_cap, hipStream_t st) {
-  k_copy_totals<<<1, 1, 0, st>>>(cnt, tot);
+  APIC_LAUNCH(k_copy_totals, dim3(1), dim3(1), 0, st, cnt, tot);
   fill_i32(smap, 0, smap_cap, &tot[5], 1, st);
   fill_i32(bmap, 0, bmap_cap, &tot[6], 1, st);
   unsigned g = (unsigned)((seg_cap * 8 + 255) / 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  k_mark<<<g, 256, 0, st>>>(seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
+  APIC_LAUNCH(k_mark, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
   scan_exclusive(smap, smap, smap_cap, &tot[5], &tot[2], partial, 1, st);
   scan_exclusive(bmap, bmap, bmap_cap, &tot[6], &tot[3], partial, 1, st);
-  k_seg_slots<<<g, 256, 0, st>>>(seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
-  k_block_counts<<<1, 1, 0, st>>>(cnt, tot, sblk_cap, bblk_cap, smap_cap, bmap_cap);
+  APIC_LAUNCH(k_seg_slots, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
+  APIC_LAUNCH(k_block_counts, dim3(1), dim3(1), 0, st, cnt, tot, sblk_cap, bblk_cap, smap_cap, bmap_cap);
+}
+
+// Block-wide reduction of 256 records: one set of atomics per block when all
+// its records name one scene, per record otherwise.
+__global__ __launch_bounds__(256) void k_reduce_red(const RedRec *rec, int64_t count_cap,
+                                                    const int32_t *count_dev,
+                                                    const Counters *cnt, double *out) {
+  __shared__ double part[kRed][4];
+  __shared__ int32_t key0;
+  if (cnt && cnt->err) return;
+  int64_t count = count_dev ? (int64_t)*count_dev : count_cap;
+  if (count > count_cap) count = count_cap;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  if (i < count) key = rec[i].key;
+  if (threadIdx.x == 0) key0 = -2;
+  __syncthreads();
+  if (key >= 0) atomicCAS(&key0, -2, key);
+  __syncthreads();
+  const int k0 = key0;
+  const bool uniform = __syncthreads_and(key < 0 || key == k0);
+  if (k0 < 0) return;
+  if (uniform) {
+    const int wave = threadIdx.x >> 6;
+    for (int c = 0; c < kRed; ++c) {
+      double v = wave_sum(key >= 0 ? rec[i].v[c] : 0.0);
+      if ((threadIdx.x & 63) == 0) part[c][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRed)
+      atomicAdd(&out[(int64_t)k0 * kRed + threadIdx.x],
+                part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                    part[threadIdx.x][3]);
+  } else if (key >= 0) {
+    for (int c = 0; c < kRed; ++c) atomicAdd(&out[(int64_t)key * kRed + c], rec[i].v[c]);
+  }
+}
+
+void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *count_dev,
+                       const Counters *cnt, double *out, hipStream_t st) {
+  if (count_cap <= 0) return;
+  APIC_LAUNCH(k_reduce_red, dim3((unsigned)((count_cap + 255) / 256)), dim3(256), 0, st, rec, count_cap, count_dev,
+                                                                     cnt, out);
 }
 
 // explicit instantiations
 template void launch_cells<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
-                                  SceneAcc *, BodyAcc *, Counters *, hipStream_t);
+                                  BodyAcc *, BoxRec *, Counters *, hipStream_t);
 template void launch_cells<double>(const double *, const uint16_t *, int64_t, const SceneDev *,
-                                   int, SceneAcc *, BodyAcc *, Counters *, hipStream_t);
+                                   int, BodyAcc *, BoxRec *, Counters *, hipStream_t);
 template void launch_keys<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
                                  const BodyLay *, uint32_t *, hipStream_t);
 template void launch_keys<double>(const double *, const uint16_t *, int64_t, const SceneDev *, int,
@@ -612,10 +788,12 @@ template void launch_keys<double>(const double *, const uint16_t *, int64_t, con
 template void launch_gather<float>(const uint32_t *, int64_t, const float *, const float *,
                                    const float *, const float *, const uint16_t *,
                                    const SceneDev *, int, float *, float *, float *, int32_t *,
-                                   float *, uint16_t *, double *, hipStream_t);
+                                   float *, uint16_t *, const uint32_t *, uint32_t *, RedRec *,
+                                   double *, hipStream_t);
 template void launch_gather<double>(const uint32_t *, int64_t, const double *, const double *,
                                     const double *, const double *, const uint16_t *,
                                     const SceneDev *, int, double *, double *, double *,
-                                    int32_t *, double *, uint16_t *, double *, hipStream_t);
+                                    int32_t *, double *, uint16_t *, const uint32_t *, uint32_t *,
+                                    RedRec *, double *, hipStream_t);
 
 }  // namespace apic

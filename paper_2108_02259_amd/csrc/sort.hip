@@ -114,9 +114,9 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_
                     int64_t *total, int32_t *partial, int mode, hipStream_t st) {
   int64_t ntiles = (n_cap + kScanTile - 1) / kScanTile;
   if (ntiles < 1) ntiles = 1;
-  k_scan_reduce<<<(unsigned)ntiles, kScanThreads, 0, st>>>(in, n_cap, n_dev, partial);
-  k_scan_partials<<<1, 1024, 0, st>>>(partial, (int)ntiles, total);
-  k_scan_down<<<(unsigned)ntiles, kScanThreads, 0, st>>>(in, out, n_cap, n_dev, partial, mode);
+  APIC_LAUNCH(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, in, n_cap, n_dev, partial);
+  APIC_LAUNCH(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, (int)ntiles, total);
+  APIC_LAUNCH(k_scan_down, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, in, out, n_cap, n_dev, partial, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,7 +137,7 @@ void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, in
   int64_t blocks = (tot + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  k_fill_i32<<<(unsigned)blocks, 256, 0, st>>>(p, value, n_cap, n_dev, scale);
+  APIC_LAUNCH(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n_cap, n_dev, scale);
 }
 
 __global__ void k_zero_u32(uint32_t *p, int64_t words) {
@@ -151,7 +151,7 @@ void fill_bytes_zero(void *p, int64_t bytes, hipStream_t st) {
   int64_t blocks = (words + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  k_zero_u32<<<(unsigned)blocks, 256, 0, st>>>((uint32_t *)p, words);
+  APIC_LAUNCH(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, words);
 }
 
 // Zero (count[0] * per) elements of `elem_bytes` bytes each, count on device.
@@ -171,7 +171,7 @@ void fill_zero_f(void *p, int64_t elems_cap, const int32_t *n_dev, int64_t per, 
   int64_t blocks = (cap + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  k_zero_counted<<<(unsigned)blocks, 256, 0, st>>>((uint32_t *)p, cap, n_dev, words_per);
+  APIC_LAUNCH(k_zero_counted, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, cap, n_dev, words_per);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,10 +261,10 @@ int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n
   uint32_t *ki = ka, *vi = va, *ko = kb, *vo = vb;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    k_radix_hist<<<(unsigned)ntiles, kSortThreads, 0, st>>>(ki, n, shift, hist, (int)ntiles);
+    APIC_LAUNCH(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, ki, n, shift, hist, (int)ntiles);
     scan_exclusive((const int32_t *)hist, (int32_t *)hist, 256 * ntiles, nullptr, total,
                    partial, 0, st);
-    k_radix_scatter<<<(unsigned)ntiles, kSortThreads, 0, st>>>(
+    APIC_LAUNCH(k_radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, 
         ki, vi, ko, vo, n, shift, (const int32_t *)hist, (int)ntiles, p == 0 ? 1 : 0);
     uint32_t *tk = ki, *tv = vi;
     ki = ko;
