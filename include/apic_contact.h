@@ -213,6 +213,56 @@ void apic_sim_destroy(apic_sim *sim);
  * admission control.  Pure host function. */
 int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec);
 
+/* ------------------------------------------------------------------------
+ * Launch tuning.
+ *
+ * The particle kernels (mass, normals, P2G and the fused rounds) run one
+ * 64-lane wave per work item of up to 64 particles.  How many waves a launch
+ * keeps per compute unit, how items are spread over the eight XCDs and how
+ * many work items of one 2x2x2-block super block a workgroup merges in LDS
+ * before its global atomics change speed but never results beyond
+ * floating-point summation order.  A context keeps one tuning per
+ * (precision, size bucket), the bucket being floor(log2(n_total)); calls and
+ * sims created afterwards use the entry of their own bucket (a sim fixes its
+ * tuning at creation).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t item_waves_per_cu; /* persistent waves per compute unit for the
+                                particle kernels, 1..64 */
+  int32_t node_wg_per_cu;    /* 256-lane workgroups per compute unit for the
+                                grid-node kernels, 1..64 */
+  int32_t xcd_split;         /* 1: each XCD works through one contiguous eighth
+                                of the (spatially sorted) items; 0: all
+                                workgroups stride over all items */
+  int32_t p2g_group;         /* 1, 4 or 8 work items of one super block per
+                                workgroup, their LDS tiles summed before the
+                                flush to the grid (FP64 uses at most 4) */
+} apic_tuning;
+
+/* Read or set the tuning a context uses for `prec` and the size bucket of n
+ * (n >= 1).  apic_set_tuning rejects out-of-range fields with
+ * APIC_E_INVALID. */
+apic_status apic_get_tuning(apic_ctx *ctx, apic_precision prec, int64_t n, apic_tuning *out);
+apic_status apic_set_tuning(apic_ctx *ctx, apic_precision prec, int64_t n,
+                            const apic_tuning *tuning);
+
+/* Autotuner: times the contact step of the given batch (same arguments and
+ * rules as apic_contact_step_batched; x, v, C, m are only read -- the timed
+ * steps write to internal copies of v and C) under each candidate tuning,
+ * `reps` timed steps per candidate after one untimed step, scoring each by
+ * the summed device time of its kernels (HIP events recorded with each
+ * dispatch).  The fastest becomes the context's tuning for (prec, bucket of
+ * n_total) and is returned in *best (host, optional); times_ms (host,
+ * optional, max_candidates entries) receives each candidate's score and
+ * candidates (host, optional) the candidates in the same order.  Returns the
+ * number of candidates tried through *n_tried (optional). */
+apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                          int32_t n_scenes, int64_t n_total, const void *x, const void *v,
+                          const void *C, const void *m, const uint16_t *body_id,
+                          apic_precision prec, int32_t reps, apic_tuning *best,
+                          apic_tuning *candidates, double *times_ms, int32_t max_candidates,
+                          int32_t *n_tried);
+
 #ifdef __cplusplus
 }
 #endif

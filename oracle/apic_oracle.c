@@ -715,12 +715,17 @@ int ora_momentum(int64_t n, const double *x, const double *v, const double *C,
  * library's own definition:
  *   cell     c_d = floor((x_d - origin_d) / h)   (FP64 division)
  *   block    B_d = floor(c_d / 4)                (4x4x4 cells per block)
+ *   pair     S_d = floor(B_d / 2)                (2x2x2 blocks per super block)
  *   body     gb  = body_base[scene] + body_id    (global body number)
- *   each body gets the box [Bmin, Bmax] of its blocks; boxes are laid end to
- *   end in global-body order (offset_gb = sum of earlier box volumes);
- *   key = (offset_gb + (Bx-Bminx) + ex ((By-Bminy) + ey (Bz-Bminz))) * 64
- *         + (cx mod 4) + 4 (cy mod 4) + 16 (cz mod 4)
- * and the permutation sorts keys ascending, equal keys by input index.
+ *   each body gets the box [Smin, Smax] of its super blocks, holding
+ *   8 * es_x * es_y * es_z block numbers (es = Smax - Smin + 1); the boxes are
+ *   laid end to end in global-body order (offset_gb = sum of earlier sizes);
+ *   block number = offset_gb
+ *                  + 8 ((Sx-Sminx) + es_x ((Sy-Sminy) + es_y (Sz-Sminz)))
+ *                  + (Bx mod 2) + 2 (By mod 2) + 4 (Bz mod 2)
+ *   key = block number * 64 + (cx mod 4) + 4 (cy mod 4) + 16 (cz mod 4)
+ * and the permutation sorts keys ascending, equal keys by input index.  The
+ * blocks of one super block of one body are thus consecutive in key order.
  * Keys must fit 32 bits (ORA_E_KEY_OVERFLOW otherwise).
  */
 typedef struct {
@@ -736,6 +741,8 @@ static int cmp_keyidx(const void *A, const void *B) {
 
 static int64_t floor_div4(int64_t c) { return c >= 0 ? c / 4 : -((-c + 3) / 4); }
 static int64_t mod4(int64_t c) { return c - 4 * floor_div4(c); }
+static int64_t floor_div2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
+static int64_t mod2(int64_t c) { return c - 2 * floor_div2(c); }
 
 int ora_cell_keys(int32_t n_scenes, const ora_grid *grids, const int64_t *offsets,
                   const int64_t *counts, const int32_t *body_base,
@@ -785,9 +792,11 @@ int ora_cell_keys(int32_t n_scenes, const ora_grid *grids, const int64_t *offset
   boff[0] = 0;
   for (int64_t b = 0; b < n_bodies_total; ++b) {
     int64_t vol = 0;
-    if (bmin[3 * b] <= bmax[3 * b])
-      vol = (bmax[3 * b] - bmin[3 * b] + 1) * (bmax[3 * b + 1] - bmin[3 * b + 1] + 1) *
-            (bmax[3 * b + 2] - bmin[3 * b + 2] + 1);
+    if (bmin[3 * b] <= bmax[3 * b]) {
+      vol = 8;
+      for (int d = 0; d < 3; ++d)
+        vol *= floor_div2(bmax[3 * b + d]) - floor_div2(bmin[3 * b + d]) + 1;
+    }
     boff[b + 1] = boff[b] + vol;
   }
   if (boff[n_bodies_total] > ((int64_t)1 << 26)) {
@@ -797,12 +806,15 @@ int ora_cell_keys(int32_t n_scenes, const ora_grid *grids, const int64_t *offset
   for (int32_t s = 0; s < n_scenes; ++s)
     for (int64_t p = offsets[s]; p < offsets[s] + counts[s]; ++p) {
       int64_t gb = gbody[p];
-      int64_t B[3], e[3];
+      int64_t S[3], es[3], sub = 0;
       for (int d = 0; d < 3; ++d) {
-        B[d] = floor_div4(cell[3 * p + d]) - bmin[3 * gb + d];
-        e[d] = bmax[3 * gb + d] - bmin[3 * gb + d] + 1;
+        const int64_t B = floor_div4(cell[3 * p + d]);
+        const int64_t smin = floor_div2(bmin[3 * gb + d]);
+        S[d] = floor_div2(B) - smin;
+        es[d] = floor_div2(bmax[3 * gb + d]) - smin + 1;
+        sub += mod2(B) << d;
       }
-      int64_t lin = boff[gb] + B[0] + e[0] * (B[1] + e[1] * B[2]);
+      int64_t lin = boff[gb] + 8 * (S[0] + es[0] * (S[1] + es[1] * S[2])) + sub;
       int64_t cib = mod4(cell[3 * p]) + 4 * mod4(cell[3 * p + 1]) + 16 * mod4(cell[3 * p + 2]);
       ki[p].key = (uint32_t)(lin * 64 + cib);
       ki[p].idx = (uint32_t)p;

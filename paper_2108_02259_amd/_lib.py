@@ -45,6 +45,11 @@ class Scene(ctypes.Structure):
                 ("n_bodies", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("item_waves_per_cu", ctypes.c_int32), ("node_wg_per_cu", ctypes.c_int32),
+                ("xcd_split", ctypes.c_int32), ("p2g_group", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point
 P = ctypes.c_void_p
 SIGNATURES = {
@@ -70,6 +75,13 @@ SIGNATURES = {
     "apic_sim_kernel_times": (ctypes.c_int, [P, P, P]),
     "apic_sim_info": (ctypes.c_int, [P, P]),
     "apic_sim_destroy": (None, [P]),
+    "apic_get_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
+    "apic_set_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
+    "apic_autotune": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32, ctypes.c_int64,
+                                     P, P, P, P, P, ctypes.c_int, ctypes.c_int32,
+                                     ctypes.POINTER(Tuning), ctypes.POINTER(Tuning),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]),
 }
 
 # kernel classes reported by apic_sim_kernel_times
@@ -121,3 +133,15 @@ def report_dict(r: Report) -> dict:
             "E_before": r.E_before, "E_after": r.E_after, "P_scale": r.P_scale,
             "L_scale": r.L_scale, "n_particles": r.n_particles,
             "n_unconstrained": r.n_unconstrained, "grid_blocks": r.grid_blocks}
+
+
+def tuning_dict(t: Tuning) -> dict:
+    return {"item_waves_per_cu": t.item_waves_per_cu, "node_wg_per_cu": t.node_wg_per_cu,
+            "xcd_split": t.xcd_split, "p2g_group": t.p2g_group}
+
+
+def make_tuning(d: dict) -> Tuning:
+    t = Tuning()
+    for k in ("item_waves_per_cu", "node_wg_per_cu", "xcd_split", "p2g_group"):
+        setattr(t, k, int(d[k]))
+    return t

@@ -24,6 +24,14 @@ def _ptr(t: torch.Tensor | None):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _prec_of_dtype(dtype) -> int:
+    if dtype in (torch.float64, "float64") or getattr(dtype, "__name__", "") == "float64":
+        return _lib.FP64
+    if dtype in (torch.float32, "float32") or getattr(dtype, "__name__", "") == "float32":
+        return _lib.FP32_MIXED
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
 def precision_of(x: torch.Tensor) -> int:
     if x.dtype == torch.float64:
         return _lib.FP64
@@ -92,6 +100,37 @@ class Context:
                                              precision_of(x), reps if report else None)
         check(rc, "apic_contact_step_batched")
         return [_lib.report_dict(r) for r in reps] if report else None
+
+    # ---- launch tuning --------------------------------------------------
+    def get_tuning(self, dtype, n: int) -> dict:
+        t = _lib.Tuning()
+        check(lib().apic_get_tuning(self._h, _prec_of_dtype(dtype), int(n), ctypes.byref(t)),
+              "apic_get_tuning")
+        return _lib.tuning_dict(t)
+
+    def set_tuning(self, dtype, n: int, tuning: dict):
+        t = _lib.make_tuning(tuning)
+        check(lib().apic_set_tuning(self._h, _prec_of_dtype(dtype), int(n), ctypes.byref(t)),
+              "apic_set_tuning")
+
+    def autotune(self, scenes, x, v, C, m, body, reps: int = 2):
+        """Time every candidate launch tuning on this batch (inputs are only
+        read) and keep the fastest for its (precision, size bucket).  Returns
+        (best, [(candidate, ms per step), ...])."""
+        n = _check_tensors(x, v, C, m, body)
+        arr = scene_table(scenes)
+        cap = 64
+        cands = (_lib.Tuning * cap)()
+        times = (ctypes.c_double * cap)()
+        best = _lib.Tuning()
+        ntried = ctypes.c_int32()
+        check(lib().apic_autotune(self._h, _stream(), arr, len(scenes), n, _ptr(x), _ptr(v),
+                                  _ptr(C), _ptr(m), _ptr(body), precision_of(x), int(reps),
+                                  ctypes.byref(best), cands, times, cap, ctypes.byref(ntried)),
+              "apic_autotune")
+        k = min(ntried.value, cap)
+        return (_lib.tuning_dict(best),
+                [(_lib.tuning_dict(cands[i]), times[i]) for i in range(k)])
 
     def sort_keys(self, scenes, x, body):
         """(sorted keys, permutation) as int64 cuda tensors."""

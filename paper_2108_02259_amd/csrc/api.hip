@@ -69,6 +69,35 @@ static apic_status status_from_err(int32_t err) {
   return APIC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// launch tuning
+// ---------------------------------------------------------------------------
+static int size_bucket(int64_t n) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << (b + 1)) <= n) ++b;
+  return b;
+}
+
+static apic_tuning default_tuning() {
+  apic_tuning t;
+  t.item_waves_per_cu = 16;
+  t.node_wg_per_cu = 8;
+  t.xcd_split = 0;
+  t.p2g_group = 4;
+  return t;
+}
+
+static bool tuning_ok(const apic_tuning &t) {
+  return t.item_waves_per_cu >= 1 && t.item_waves_per_cu <= 64 && t.node_wg_per_cu >= 1 &&
+         t.node_wg_per_cu <= 64 && (t.xcd_split == 0 || t.xcd_split == 1) &&
+         (t.p2g_group == 1 || t.p2g_group == 4 || t.p2g_group == 8);
+}
+
+apic_tuning apic_ctx::tuning_for(apic_precision prec, int64_t n) const {
+  auto it = tuning.find({(int)prec, size_bucket(n)});
+  return it == tuning.end() ? default_tuning() : it->second;
+}
+
 apic_status apic_ctx::host_stage(size_t bytes) {
   if (stage_bytes >= bytes) return APIC_OK;
   if (stage) (void)hipHostFree(stage);
@@ -190,10 +219,30 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.smap_cap = std::max<int64_t>(1, (int64_t)std::ceil(smap_total * headroom));
   P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
   P.seg_cap = std::max<int64_t>(n, 1);
-  P.item_cap = n + n / kItem + 1;
+  // items: at most one per particle plus one per 64, plus the run padding
+  // (fewer than kRunAlign per run, one run per super block of a body, and a
+  // body's super blocks number kRunAlign block keys each)
+  P.item_cap = n + n / kItem + 1 + kb;
   P.sblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.smap_cap, 8 * n));
   P.bblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.bmap_cap, 8 * n));
-  P.grid_wg = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->persistent_wg, (n + 63) / 64 * 2));
+  const apic_tuning tu = ctx->tuning_for(P.prec, n);
+  {
+    // particle kernels: a multiple of 8 workgroups (one share per XCD), never
+    // more than twice the items a dense layout has; grouped kernels run
+    // `group` waves per workgroup (FP64 at most 4: LDS)
+    const int64_t cus = std::max(1, ctx->cus);
+    const int grp = (P.prec == APIC_FP64) ? std::min(tu.p2g_group, 4) : tu.p2g_group;
+    const int64_t dense_items = (n + 63) / 64 * 2;
+    auto round8 = [](int64_t v) { return std::max<int64_t>(8, (v + 7) / 8 * 8); };
+    P.item_wg = (int)round8(std::min<int64_t>(cus * tu.item_waves_per_cu, dense_items));
+    P.grid_wg = (int)round8(std::min<int64_t>(cus * tu.item_waves_per_cu / grp,
+                                              (dense_items + grp - 1) / grp));
+    int64_t gn = cus * tu.node_wg_per_cu;
+    gn = std::min<int64_t>(gn, (P.sblk_cap * kNodesPerBlock + 255) / 256);
+    P.node_wg = (int)std::max<int64_t>(1, gn);
+    P.xcd_split = tu.xcd_split;
+    P.group = grp;
+  }
   const int64_t ntiles = std::max<int64_t>(sort_tiles(n), 1);
   const size_t T = P.tbytes;
   TRY(W.ensure(kKeysA, sizeof(uint32_t) * n));
@@ -308,6 +357,10 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.keys = P.keys;
   a.n = n;
   a.grid_wg = P.grid_wg;
+  a.node_wg = P.node_wg;
+  a.xcd_split = P.xcd_split;
+  a.item_wg = P.item_wg;
+  a.group = P.group;
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
   launch_mass<T>(a, t, m_sorted, P.g, st);
@@ -588,7 +641,6 @@ apic_status apic_create(apic_ctx **out, int device, size_t hbm_budget_bytes) {
   c->device = device;
   c->ws.budget = hbm_budget_bytes;
   c->cus = prop.multiProcessorCount;
-  c->persistent_wg = std::max(1, prop.multiProcessorCount) * 16;
   *out = c;
   return APIC_OK;
 }
@@ -858,6 +910,124 @@ void apic_sim_destroy(apic_sim *S) {
   S->prof.release();
   S->ws.release();
   delete S;
+}
+
+apic_status apic_get_tuning(apic_ctx *ctx, apic_precision prec, int64_t n, apic_tuning *out) {
+  if (!ctx || !out || n < 1 || (prec != APIC_FP64 && prec != APIC_FP32_MIXED))
+    return APIC_E_INVALID;
+  *out = ctx->tuning_for(prec, n);
+  return APIC_OK;
+}
+
+apic_status apic_set_tuning(apic_ctx *ctx, apic_precision prec, int64_t n,
+                            const apic_tuning *tuning) {
+  if (!ctx || !tuning || n < 1 || (prec != APIC_FP64 && prec != APIC_FP32_MIXED) ||
+      !tuning_ok(*tuning))
+    return APIC_E_INVALID;
+  ctx->tuning[{(int)prec, size_bucket(n)}] = *tuning;
+  return APIC_OK;
+}
+
+apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                          int32_t n_scenes, int64_t n_total, const void *x, const void *v,
+                          const void *C, const void *m, const uint16_t *body_id,
+                          apic_precision prec, int32_t reps, apic_tuning *best,
+                          apic_tuning *candidates, double *times_ms, int32_t max_candidates,
+                          int32_t *n_tried) {
+  if (!ctx || reps < 1 || reps > 100 || n_total < 1) return APIC_E_INVALID;
+  TRY(validate_scenes(scenes, n_scenes, n_total));
+  if (!x || !v || !C || !m || !body_id) return APIC_E_INVALID;
+  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
+  if ((times_ms || candidates) && max_candidates < 0) return APIC_E_INVALID;
+  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t tb = prec == APIC_FP64 ? 8 : 4;
+  TRY(ctx->ws.ensure(kTuneV, tb * 3 * n_total));
+  TRY(ctx->ws.ensure(kTuneC, tb * 9 * n_total));
+  void *tv = ctx->ws.ptr[kTuneV], *tC = ctx->ws.ptr[kTuneC];
+  const std::pair<int, int> key{(int)prec, size_bucket(n_total)};
+  const bool had = ctx->tuning.count(key) != 0;
+  const apic_tuning before = ctx->tuning_for(prec, n_total);
+
+  // one step on fresh copies of v and C, optionally with every launch timed
+  Profiler prof;
+  prof.on = true;
+  auto run = [&](bool timed) -> apic_status {
+    HIPOK(hipMemcpyAsync(tv, v, tb * 3 * n_total, hipMemcpyDeviceToDevice, st));
+    HIPOK(hipMemcpyAsync(tC, C, tb * 9 * n_total, hipMemcpyDeviceToDevice, st));
+    if (timed) prof.begin(st);
+    apic_status rc =
+        prec == APIC_FP64
+            ? step_impl<double>(ctx, st, scenes, n_scenes, n_total, (const double *)x,
+                                (double *)tv, (double *)tC, (const double *)m, body_id, nullptr)
+            : step_impl<float>(ctx, st, scenes, n_scenes, n_total, (const float *)x, (float *)tv,
+                               (float *)tC, (const float *)m, body_id, nullptr);
+    if (timed) prof.end(0, st);
+    return rc;
+  };
+  auto score = [&](const apic_tuning &t, double *ms) -> apic_status {
+    ctx->tuning[key] = t;
+    TRY(run(false));
+    for (int k = 0; k < APIC_KC_COUNT; ++k) prof.total_ms[k] = 0.0, prof.launches[k] = 0;
+    for (int r = 0; r < reps; ++r) TRY(run(true));
+    HIPOK(hipStreamSynchronize(st));
+    prof.collect();
+    *ms = prof.total_ms[0] / reps;
+    return APIC_OK;
+  };
+
+  std::vector<apic_tuning> tried;
+  std::vector<double> times;
+  apic_status rc = APIC_OK;
+  apic_tuning bestt = before;
+  double best_ms = 1e300;
+  // stage 1: work items merged per workgroup, waves per CU, XCD split
+  const int group_opts[] = {1, 4, 8};
+  const int wave_opts[] = {8, 16, 24, 32};
+  for (int grp : group_opts) {
+    if (prec == APIC_FP64 && grp > 4) continue;
+    for (int xs = 0; xs < 2 && rc == APIC_OK; ++xs)
+      for (int wv : wave_opts) {
+        apic_tuning t = before;
+        t.item_waves_per_cu = wv;
+        t.xcd_split = xs;
+        t.p2g_group = grp;
+        double ms = 0;
+        rc = score(t, &ms);
+        if (rc != APIC_OK) break;
+        tried.push_back(t);
+        times.push_back(ms);
+        if (ms < best_ms) best_ms = ms, bestt = t;
+      }
+    if (rc != APIC_OK) break;
+  }
+  // stage 2: node-kernel launch shape with the best of stage 1
+  const int node_opts[] = {4, 8, 16, 32};
+  const apic_tuning stage1 = bestt;
+  for (int nw : node_opts) {
+    if (rc != APIC_OK) break;
+    apic_tuning t = stage1;
+    t.node_wg_per_cu = nw;
+    double ms = 0;
+    rc = score(t, &ms);
+    if (rc != APIC_OK) break;
+    tried.push_back(t);
+    times.push_back(ms);
+    if (ms < best_ms) best_ms = ms, bestt = t;
+  }
+  prof.release();
+  if (rc != APIC_OK) {
+    if (had) ctx->tuning[key] = before; else ctx->tuning.erase(key);
+    return rc;
+  }
+  ctx->tuning[key] = bestt;
+  if (best) *best = bestt;
+  for (int i = 0; i < (int)tried.size() && i < max_candidates; ++i) {
+    if (candidates) candidates[i] = tried[i];
+    if (times_ms) times_ms[i] = times[i];
+  }
+  if (n_tried) *n_tried = (int32_t)tried.size();
+  return APIC_OK;
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "apic_contact.h"
@@ -15,7 +17,7 @@ namespace apic {
 enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
   kValsB, kHist, kPartial, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
-  kFlags, kItems, kSmap, kBmap, kGMass, kGBuf0, kGBuf1, kBMass, kBoxRec, kRecGather, kRecItems, kNumBufs
+  kFlags, kItems, kSmap, kBmap, kGMass, kGBuf0, kGBuf1, kBMass, kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
 };
 
 // Grow-only device buffers, bounded by an HBM budget.
@@ -40,6 +42,10 @@ struct Plan {
   int sort_bits = 32;
   int64_t seg_cap = 0, item_cap = 0, smap_cap = 0, bmap_cap = 0, sblk_cap = 0, bblk_cap = 0;
   int grid_wg = 1;
+  int item_wg = 1;
+  int node_wg = 1;
+  int xcd_split = 0;
+  int group = 1;
   bool ready = false;
   SceneDev *sc = nullptr;
   SceneAcc *sacc = nullptr;
@@ -114,8 +120,10 @@ void launch_unpermute(const uint32_t *orig, int64_t n, const T *x_sorted, const 
 struct apic_ctx {
   int device = 0;
   int cus = 0;
-  int persistent_wg = 2048;
   apic::Workspace ws;
+  // launch tuning per (precision, floor(log2 n))
+  std::map<std::pair<int, int>, apic_tuning> tuning;
+  apic_tuning tuning_for(apic_precision prec, int64_t n) const;
   void *stage = nullptr;  // pinned host staging
   size_t stage_bytes = 0;
   apic_status host_stage(size_t bytes);

@@ -80,10 +80,15 @@ struct SceneLay {
   int32_t sext[3];       // node-block map extent (= box extent + 1)
 };
 
+// A body's key range numbers its blocks super block by super block (2x2x2
+// blocks each, over the body's super-block box, x fastest), so that the
+// blocks of one super block of one body are consecutive in key order.
 struct BodyLay {
   int64_t bmap_off;      // offset of this body's node-block map
   int32_t bmin[3];       // cell-block box min
   int32_t ext[3];        // cell-block box extent (0 if empty)
+  int32_t kmin[3];       // super-block box min (floor(bmin / 2))
+  int32_t kext[3];       // super-block box extent (0 if empty)
   int32_t key_off;       // first key block of this body
   int32_t scene;
 };
@@ -98,6 +103,11 @@ struct Segment {
   int32_t bslot[8];      // body-grid node-block slots
 };
 
+// A work item: up to kItem particles of one segment.  The items of one
+// (body, super block) run are consecutive and padded with empty items
+// (count 0) to a multiple of kRunAlign, so that aligned groups of 1, 4 or 8
+// items never straddle two runs.
+constexpr int kRunAlign = 8;
 struct Item {
   int32_t seg, start, count, pad;
 };

@@ -85,7 +85,11 @@ struct StepArgs {
   const Counters *cnt;
   const uint32_t *keys;  // sorted
   int64_t n;
-  int grid_wg;           // persistent workgroups
+  int grid_wg;           // workgroups of the grouped particle kernels (64*group lanes)
+  int item_wg;           // workgroups of the one-wave particle kernels
+  int node_wg;           // 256-lane workgroups of the node kernels
+  int xcd_split;         // 1: each XCD walks one contiguous eighth of the items
+  int group;             // work items merged per workgroup before the flush (1, 4, 8)
 };
 
 template <typename T>

@@ -259,11 +259,11 @@ __global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, in
       ba = bacc[gb];
       ne = ba.bmin[0] <= ba.bmax[0];
       if (ne) {
-        kv = 1;
+        kv = 8;
         mv = 1;
         for (int d = 0; d < 3; ++d) {
           int64_t e = (int64_t)(ba.bmax[d] - ba.bmin[d] + 1);
-          kv *= e;
+          kv *= (int64_t)((ba.bmax[d] >> 1) - (ba.bmin[d] >> 1) + 1);
           mv *= e + 1;
         }
       }
@@ -280,6 +280,8 @@ __global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, in
       for (int d = 0; d < 3; ++d) {
         bl.bmin[d] = ne ? ba.bmin[d] : 0;
         bl.ext[d] = ne ? ba.bmax[d] - ba.bmin[d] + 1 : 0;
+        bl.kmin[d] = ne ? ba.bmin[d] >> 1 : 0;
+        bl.kext[d] = ne ? (ba.bmax[d] >> 1) - (ba.bmin[d] >> 1) + 1 : 0;
       }
       blay[gb] = bl;
       if (ne)
@@ -352,10 +354,15 @@ __global__ __launch_bounds__(256) void k_keys(const T *x, const uint16_t *body, 
   uint32_t key = 0;
   if (ci.ok && b < sd.n_bodies) {
     const BodyLay bl = blay[sd.body_base + b];
-    int32_t L[3];
+    int32_t L[3], sub = 0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) L[d] = floor_div4(ci.c[d]) - bl.bmin[d];
-    int64_t lin = (int64_t)bl.key_off + L[0] + (int64_t)bl.ext[0] * (L[1] + (int64_t)bl.ext[1] * L[2]);
+    for (int d = 0; d < 3; ++d) {
+      const int32_t B = floor_div4(ci.c[d]);
+      L[d] = (B >> 1) - bl.kmin[d];
+      sub |= (B & 1) << d;
+    }
+    int64_t lin = (int64_t)bl.key_off +
+                  8 * (L[0] + (int64_t)bl.kext[0] * (L[1] + (int64_t)bl.kext[1] * L[2])) + sub;
     int cib = (ci.c[0] & 3) | ((ci.c[1] & 3) << 2) | ((ci.c[2] & 3) << 4);
     if (lin < kMaxKeyBlocks) key = (uint32_t)(lin * 64 + cib);
   }
@@ -566,11 +573,13 @@ __global__ void k_seg_heads(const uint32_t *keys, int64_t n, const int32_t *segi
     }
     const int gb = sbody[i];
     const BodyLay bl = blay[gb];
-    int64_t local = (int64_t)(keys[i] >> 6) - bl.key_off;
-    int ex = bl.ext[0] > 0 ? bl.ext[0] : 1, ey = bl.ext[1] > 0 ? bl.ext[1] : 1;
-    int lx = (int)(local % ex);
-    int ly = (int)((local / ex) % ey);
-    int lz = (int)(local / ((int64_t)ex * ey));
+    const int64_t local = (int64_t)(keys[i] >> 6) - bl.key_off;
+    const int sub = (int)(local & 7);
+    const int64_t sl = local >> 3;
+    const int ex = bl.kext[0] > 0 ? bl.kext[0] : 1, ey = bl.kext[1] > 0 ? bl.kext[1] : 1;
+    const int lx = 2 * (bl.kmin[0] + (int)(sl % ex)) + (sub & 1) - bl.bmin[0];
+    const int ly = 2 * (bl.kmin[1] + (int)((sl / ex) % ey)) + ((sub >> 1) & 1) - bl.bmin[1];
+    const int lz = 2 * (bl.kmin[2] + (int)(sl / ((int64_t)ex * ey))) + ((sub >> 2) & 1) - bl.bmin[2];
     Segment sg;
     sg.start = (int32_t)i;
     sg.count = 0;
@@ -589,16 +598,37 @@ __global__ void k_seg_heads(const uint32_t *keys, int64_t n, const int32_t *segi
 }
 
 // counts from consecutive starts; items per segment into tmp.
+// Segments of one body whose blocks lie in one 2x2x2 super block (a run: at
+// most 8 consecutive segments, one per block).
+__device__ __forceinline__ bool same_run(const Segment &a, const Segment &b) {
+  return a.body == b.body && (a.B[0] >> 1) == (b.B[0] >> 1) && (a.B[1] >> 1) == (b.B[1] >> 1) &&
+         (a.B[2] >> 1) == (b.B[2] >> 1);
+}
+
+__device__ __forceinline__ int32_t seg_items(const Segment *seg, int64_t k, int64_t ns, int64_t n) {
+  const int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
+  return (int32_t)((end - seg[k].start + kItem - 1) / kItem);
+}
+
+// Particle count and item count of every segment; the last segment of a run
+// also takes the run's padding items.
 __global__ void k_seg_counts(Segment *seg, int64_t seg_cap, const int64_t *nseg_dev, int64_t n,
                              int32_t *nitems, Counters *cnt) {
   int64_t ns = *nseg_dev;
   if (ns > seg_cap) ns = seg_cap;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
        k += (int64_t)gridDim.x * blockDim.x) {
+    const Segment sk = seg[k];
     int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
-    int32_t c = (int32_t)(end - seg[k].start);
-    seg[k].count = c;
-    nitems[k] = (c + kItem - 1) / kItem;
+    seg[k].count = (int32_t)(end - sk.start);
+    int32_t items = seg_items(seg, k, ns, n);
+    if (k + 1 == ns || !same_run(seg[k + 1], sk)) {
+      int32_t run = items;
+      for (int64_t h = k - 1; h >= 0 && k - h < kRunAlign && same_run(seg[h], sk); --h)
+        run += seg_items(seg, h, ns, n);
+      items += (kRunAlign - run % kRunAlign) % kRunAlign;
+    }
+    nitems[k] = items;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_seg = (int32_t)ns;
 }
@@ -611,17 +641,19 @@ __global__ void k_items(const Segment *seg, int64_t seg_cap, const int64_t *nseg
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
        k += (int64_t)gridDim.x * blockDim.x) {
     const Segment sg = seg[k];
-    int32_t off = item_off[k];
-    for (int32_t s = 0; s < sg.count; s += kItem) {
-      int64_t w = off + s / kItem;
+    const int64_t off = item_off[k];
+    const int64_t end = (k + 1 < ns) ? (int64_t)item_off[k + 1] : *nitems_dev;
+    // real items, then (last segment of a run) empty padding items
+    for (int64_t w = off; w < end; ++w) {
       if (w >= item_cap) {
         atomicOr(&cnt->err, kErrCapacity);
         break;
       }
+      const int32_t s = (int32_t)(w - off) * kItem;
       Item it;
       it.seg = (int32_t)k;
-      it.start = sg.start + s;
-      it.count = min(kItem, sg.count - s);
+      it.start = sg.start + (s < sg.count ? s : 0);
+      it.count = s < sg.count ? min(kItem, sg.count - s) : 0;
       it.pad = 0;
       items[w] = it;
     }

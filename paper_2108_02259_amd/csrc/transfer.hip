@@ -347,24 +347,162 @@ __device__ __forceinline__ int item_count(const StepArgs &a) {
   return a.cnt->err ? 0 : a.cnt->n_items;
 }
 
+// Work-item schedule of the particle kernels.  Workgroups are dispatched to
+// the eight XCDs in turn (workgroup b runs on XCD b mod 8), each XCD with its
+// own L2.  With xcd_split the item list (sorted, so neighbouring items share
+// node blocks) is cut into eight contiguous ranges and the workgroups of XCD x
+// walk range x, which keeps a node block's tile loads and flush atomics in one
+// L2; otherwise every workgroup strides over the whole list.
+struct ItemLoop {
+  int w, end, step;
+};
+
+// Units of `unit` consecutive items (a multiple of the run padding
+// divides every run, so a unit never straddles two runs).
+__device__ __forceinline__ ItemLoop item_loop(const StepArgs &a, int unit = 1) {
+  const int nitems = item_count(a) / unit;
+  ItemLoop L;
+  if (a.xcd_split) {  // the host keeps gridDim.x a multiple of 8 in this mode
+    const int per = gridDim.x >> 3;
+    const int chunk = (nitems + 7) >> 3;
+    const int lo = (blockIdx.x & 7) * chunk;
+    L.w = lo + (blockIdx.x >> 3);
+    L.end = min(nitems, lo + chunk);
+    L.step = per;
+  } else {
+    L.w = blockIdx.x;
+    L.end = nitems;
+    L.step = gridDim.x;
+  }
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Work-item groups
+// ---------------------------------------------------------------------------
+// The items of one (body, super block) run are consecutive -- the cell key
+// numbers a body's blocks super block by super block -- and padded with
+// empty items to a multiple of 8.  A group is the G aligned items g*G ..
+// g*G + G - 1, all of one run; empty items have no particles.  The G waves
+// of a workgroup take one item each and scatter into their own
+// LDS tiles; the workgroup then merges the tiles node by node over the 3x3x3
+// node blocks of the super block, so a node leaves the workgroup in one
+// global atomic instead of one per item.  With G = 1 each wave flushes its
+// own tile.
+template <int G>
+struct GroupLds {
+  int32_t slot[27];   // shared-grid slot of super node block J (-1: none)
+  uint32_t mask[27];  // waves whose tile covers J
+  int32_t sbi[G];     // wave's block within the super block, x + 2y + 4z
+  int32_t seg[G];     // wave's segment, -1 if it has nothing to flush
+};
+
+__device__ __forceinline__ int block_in_super(const Segment &sg) {
+  return (sg.B[0] & 1) | ((sg.B[1] & 1) << 1) | ((sg.B[2] & 1) << 2);
+}
+
+// Cover masks and slots of the 27 node blocks (after every wave has filled
+// its sbi/seg entry and a barrier).
+template <int G>
+__device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl) {
+  const int t = threadIdx.x;
+  if (t < 27) {
+    const int Jx = t % 3, Jy = (t / 3) % 3, Jz = t / 9;
+    uint32_t mask = 0;
+    int32_t slot = -1;
+    for (int w = 0; w < G; ++w) {
+      const int sgi = gl.seg[w];
+      if (sgi < 0) continue;
+      const int sb = gl.sbi[w];
+      const int jx = Jx - (sb & 1), jy = Jy - ((sb >> 1) & 1), jz = Jz - (sb >> 2);
+      if (jx < 0 || jx > 1 || jy < 0 || jy > 1 || jz < 0 || jz > 1) continue;
+      mask |= 1u << w;
+      slot = a.seg[sgi].sslot[jx + 2 * jy + 4 * jz];
+    }
+    gl.mask[t] = mask;
+    gl.slot[t] = slot;
+  }
+}
+
+// Sum the covering waves' tiles per node (wave order) and add each nonzero
+// sum once to the global buffer; the tiles read are left zero.
+template <typename T, int G, int NC>
+__device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const GroupLds<G> &gl,
+                                            T *buf, int comps_in_buf) {
+  for (int idx = threadIdx.x; idx < 27 * kNodesPerBlock; idx += 64 * G) {
+    const int J = idx >> 6, node = idx & 63;
+    const uint32_t mask = gl.mask[J];
+    if (!mask) continue;
+    const int Jx = J % 3, Jy = (J / 3) % 3, Jz = J / 9;
+    T sum[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sum[q] = T(0);
+#pragma unroll
+    for (int w = 0; w < G; ++w) {
+      if (!((mask >> w) & 1u)) continue;
+      const int sb = gl.sbi[w];
+      const int j = (Jx - (sb & 1)) + 2 * (Jy - ((sb >> 1) & 1)) + 4 * (Jz - (sb >> 2));
+      const int li = tile_index_block(j, node);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        sum[q] += tiles[w][q][li];
+        tiles[w][q][li] = T(0);
+      }
+    }
+    const int s = gl.slot[J];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+      if (sum[q] != T(0) && s >= 0)
+        unsafeAtomicAdd(&buf[((int64_t)s * comps_in_buf + q) * kNodesPerBlock + node], sum[q]);
+  }
+}
+
+// Flush of a group's shared-grid tiles: each wave's own tile when G = 1,
+// else the merged tiles (all threads of the workgroup take part).
+template <typename T, int G, int NC>
+__device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kTileSize],
+                                            GroupLds<G> &gl, bool flushes, int seg_index,
+                                            T *buf, int comps_in_buf) {
+  if (G == 1) {
+    wave_sync();
+    if (flushes) flush_tile<T, NC>(tiles[0], buf, a.seg[seg_index].sslot, comps_in_buf);
+    wave_sync();
+  } else {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      gl.seg[wave] = flushes ? seg_index : -1;
+      gl.sbi[wave] = flushes ? block_in_super(a.seg[seg_index]) : 0;
+    }
+    __syncthreads();
+    group_tables<G>(a, gl);
+    __syncthreads();
+    group_flush<T, G, NC>(tiles, gl, buf, comps_in_buf);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // grid mass and per-body mass
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
+template <typename T, int G>
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
-  __shared__ T tm[1][kTileSize];
-  __shared__ T tb[1][kTileSize];  // one item's body mass; flushed into FP64
-  zero_tile<T, 1>(tm);
-  zero_tile<T, 1>(tb);
+  __shared__ T tm[G][1][kTileSize];
+  __shared__ T tb[G][1][kTileSize];  // one item's body mass; flushed into FP64
+  __shared__ GroupLds<G> gl;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  zero_tile<T, 1>(tm[wave]);
+  zero_tile<T, 1>(tb[wave]);
   wave_sync();
-  const int lane = threadIdx.x;
-  const int nitems = item_count(a);
   const int64_t n = a.n;
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const Item it = a.items[w];
+  for (ItemLoop L = item_loop(a, G); L.w < L.end; L.w += L.step) {
+    const int w0 = L.w * G;
+    if (a.items[w0].count == 0) continue;  // padding only (uniform over the workgroup)
+    const Item mine = a.items[w0 + wave];
+    const bool member = mine.count > 0;
+    const Item it = member ? mine : a.items[w0];
     const Segment &sg = a.seg[it.seg];
-    const bool active = lane < it.count;
+    const bool active = member && lane < it.count;
     const int64_t i = it.start + (active ? lane : 0);
     const uint32_t key = a.keys[i];
     int passes;
@@ -377,14 +515,13 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
       const T mp = m[i];
       const int base = particle_base(key);
       for (int pass = 0; pass < passes; ++pass) {
-        if (rank == pass) p2g_mass(&tm[0][0], &tb[0][0], base, S, mp);
+        if (rank == pass) p2g_mass(&tm[wave][0][0], &tb[wave][0][0], base, S, mp);
         LDS_ORDER();
       }
     }
     wave_sync();
-    flush_tile<T, 1>(tm, (T *)g.mass, sg.sslot, 1);
-    flush_tile_to<T, double>(tb, g.bmass, sg.bslot);
-    wave_sync();
+    if (member) flush_tile_to<T, double>(tb[wave], g.bmass, sg.bslot);
+    flush_group<T, G, 1>(a, tm, gl, member, it.seg, (T *)g.mass, 1);
   }
 }
 
@@ -395,10 +532,11 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_normals(StepArgs a, const T *t, T *nrm, GridPtrs g) {
   __shared__ double tb[1][kTileSize];
   const int lane = threadIdx.x;
-  const int nitems = item_count(a);
   const int64_t n = a.n;
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+  for (ItemLoop L = item_loop(a); L.w < L.end; L.w += L.step) {
+    const int w = L.w;
     const Item it = a.items[w];
+    if (it.count == 0) continue;  // run padding
     const Segment &sg = a.seg[it.seg];
     const SceneDev &sd = a.sc[sg.scene];
     if (sd.n_iter == 0) continue;  // no series, normals unused
@@ -421,19 +559,23 @@ __global__ __launch_bounds__(64) void k_normals(StepArgs a, const T *t, T *nrm, 
 // ---------------------------------------------------------------------------
 // P2G of Vbar into buffer 0
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
+template <typename T, int G>
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
-  __shared__ T tq[3][kTileSize];
-  zero_tile<T, 3>(tq);
+  __shared__ T tq[G][3][kTileSize];
+  __shared__ GroupLds<G> gl;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  zero_tile<T, 3>(tq[wave]);
   wave_sync();
-  const int lane = threadIdx.x;
-  const int nitems = item_count(a);
   const int64_t n = a.n;
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const Item it = a.items[w];
+  for (ItemLoop L = item_loop(a, G); L.w < L.end; L.w += L.step) {
+    const int w0 = L.w * G;
+    if (a.items[w0].count == 0) continue;  // padding only (uniform over the workgroup)
+    const Item mine = a.items[w0 + wave];
+    const bool member = mine.count > 0;
+    const Item it = member ? mine : a.items[w0];
     const Segment &sg = a.seg[it.seg];
-    const bool active = lane < it.count;
+    const bool active = member && lane < it.count;
     const int64_t i = it.start + (active ? lane : 0);
     const uint32_t key = a.keys[i];
     int passes;
@@ -451,13 +593,11 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
       const T mp = m[i];
       const int base = particle_base(key);
       for (int pass = 0; pass < passes; ++pass) {
-        if (rank == pass) p2g(tq, base, S, mp, u, E);
+        if (rank == pass) p2g(tq[wave], base, S, mp, u, E);
         LDS_ORDER();
       }
     }
-    wave_sync();
-    flush_tile<T, 3>(tq, (T *)g.buf[0], sg.sslot, 3);
-    wave_sync();
+    flush_group<T, G, 3>(a, tq, gl, member, it.seg, (T *)g.buf[0], 3);
   }
 }
 
@@ -491,26 +631,31 @@ __global__ __launch_bounds__(256) void k_gridvel(const Counters *cnt, const T *m
 // answer is Vhat = Vbar + D_N.  Round 1 starts from D_0 = H Vbar - Vbar.
 // Scenes with n_iter == k-1 finish in round k: they write Vhat and scatter
 // nothing.  FINAL rounds only finish.
-template <typename T, bool FIRST, bool FINAL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
+template <typename T, bool FIRST, bool FINAL, int G>
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
 void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *nrm, T *Y,
             GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out) {
-  // One tile: the gathered grid velocities, then (cleared) the scatter target.
-  __shared__ T tile[3][kTileSize];
-  const int lane = threadIdx.x;
-  const int nitems = item_count(a);
+  // One tile per wave: the gathered grid velocities, then (cleared) the
+  // scatter target.
+  __shared__ T tile[G][3][kTileSize];
+  __shared__ GroupLds<G> gl;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n = a.n;
   const T *gcur = (const T *)g.buf[cur];
   T *gnext = (T *)g.buf[1 - cur];
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const Item it = a.items[w];
+  for (ItemLoop L = item_loop(a, G); L.w < L.end; L.w += L.step) {
+    const int w0 = L.w * G;
+    if (a.items[w0].count == 0) continue;  // padding only (uniform over the workgroup)
+    const Item mine = a.items[w0 + wave];
+    const bool member = mine.count > 0;
+    const Item it = member ? mine : a.items[w0];
     const Segment &sg = a.seg[it.seg];
     const SceneDev &sd = a.sc[sg.scene];
-    if (sd.n_iter < k - 1) continue;  // scene already finished (uniform per item)
+    if (sd.n_iter < k - 1) continue;  // scene already finished (uniform per group)
     const bool finishing = FINAL || sd.n_iter == k - 1;
-    load_tile<T, 3>(tile, gcur, sg.sslot, 3);
+    if (member) load_tile<T, 3>(tile[wave], gcur, sg.sslot, 3);
     wave_sync();
-    const bool active = lane < it.count;
+    const bool active = member && lane < it.count;
     const int64_t i = it.start + (active ? lane : 0);
     const uint32_t key = a.keys[i];
     const int base = particle_base(key);
@@ -522,7 +667,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       load_t(t, n, i, tt);
       make_stencil(tt, h, S);
       T hv[3], hC[9];
-      g2p(tile, base, S, T(2) / (h * h), hv, hC);
+      g2p(tile[wave], base, S, T(2) / (h * h), hv, hC);
       if (finishing) {
         const int64_t dst = perm ? (int64_t)perm[i] : i;
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
@@ -572,60 +717,84 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       int passes = 0;
       const int rank = cell_rank(active, key & 63u, &passes);
       wave_sync();
-      zero_tile<T, 3>(tile);
+      if (member) zero_tile<T, 3>(tile[wave]);
       wave_sync();
       if (active) {
         const T mp = m[i];
         for (int pass = 0; pass < passes; ++pass) {
-          if (rank == pass) p2g(tile, base, S, mp, W, W + 3);
+          if (rank == pass) p2g(tile[wave], base, S, mp, W, W + 3);
           LDS_ORDER();
         }
       }
-      wave_sync();
-      flush_tile<T, 3>(tile, gnext, sg.sslot, 3);
+      flush_group<T, G, 3>(a, tile, gl, member, it.seg, gnext, 3);
     }
     wave_sync();
   }
 }
 
+// Workgroup shape of the grouped kernels: a.group waves (1, 4 or 8).
+#define APIC_GROUP_DISPATCH(KERNEL_G, ...)          \
+  do {                                              \
+    if (a.group >= 8 && sizeof(T) == 4) {          \
+      constexpr int G_ = 8;                         \
+      KERNEL_G(__VA_ARGS__);                        \
+    } else if (a.group >= 4) {                      \
+      constexpr int G_ = 4;                         \
+      KERNEL_G(__VA_ARGS__);                        \
+    } else {                                        \
+      constexpr int G_ = 1;                         \
+      KERNEL_G(__VA_ARGS__);                        \
+    }                                               \
+  } while (0)
+
 template <typename T>
 void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStream_t st) {
-  APIC_LAUNCH((k_mass<T>), dim3(a.grid_wg), dim3(64), 0, st, a, t, m, g);
+#define L_MASS() APIC_LAUNCH((k_mass<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, g)
+  APIC_GROUP_DISPATCH(L_MASS);
+#undef L_MASS
 }
 
 template <typename T>
 void launch_normals(const StepArgs &a, const T *t, T *nrm, GridPtrs g, hipStream_t st) {
-  APIC_LAUNCH((k_normals<T>), dim3(a.grid_wg), dim3(64), 0, st, a, t, nrm, g);
+  APIC_LAUNCH((k_normals<T>), dim3(a.item_wg), dim3(64), 0, st, a, t, nrm, g);
 }
 
 template <typename T>
 void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
                  hipStream_t st) {
-  APIC_LAUNCH((k_p2g0<T>), dim3(a.grid_wg), dim3(64), 0, st, a, t, m, vbar, g);
+#define L_P2G0() APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, g)
+  APIC_GROUP_DISPATCH(L_P2G0);
+#undef L_P2G0
 }
 
 template <typename T>
 void launch_gridvel(const StepArgs &a, GridPtrs g, int cur, hipStream_t st) {
-  APIC_LAUNCH((k_gridvel<T>), dim3(a.grid_wg * 2), dim3(256), 0, st, a.cnt, (const T *)g.mass, (T *)g.buf[cur],
-                                               (T *)g.buf[1 - cur]);
+  APIC_LAUNCH((k_gridvel<T>), dim3(a.node_wg), dim3(256), 0, st, a.cnt, (const T *)g.mass,
+              (T *)g.buf[cur], (T *)g.buf[1 - cur]);
 }
 
 template <typename T>
 void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
                  const T *nrm, T *Y, GridPtrs g, int cur, const uint32_t *perm, T *v_out,
                  T *C_out, hipStream_t st) {
-  if (k == 1 && final)
-    APIC_LAUNCH((k_iter<T, true, true>), dim3(a.grid_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y, g, cur, perm, v_out,
-                                                     C_out);
-  else if (k == 1)
-    APIC_LAUNCH((k_iter<T, true, false>), dim3(a.grid_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y, g, cur, perm,
-                                                      v_out, C_out);
-  else if (final)
-    APIC_LAUNCH((k_iter<T, false, true>), dim3(a.grid_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y, g, cur, perm,
-                                                      v_out, C_out);
+  // finishing-only rounds scatter nothing: one wave per item
+  if (final) {
+    if (k == 1)
+      APIC_LAUNCH((k_iter<T, true, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m, vbar,
+                  nrm, Y, g, cur, perm, v_out, C_out);
+    else
+      APIC_LAUNCH((k_iter<T, false, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m,
+                  vbar, nrm, Y, g, cur, perm, v_out, C_out);
+    return;
+  }
+#define L_ITER(FIRST_) \
+  APIC_LAUNCH((k_iter<T, FIRST_, false, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
+              vbar, nrm, Y, g, cur, perm, v_out, C_out)
+  if (k == 1)
+    APIC_GROUP_DISPATCH(L_ITER, true);
   else
-    APIC_LAUNCH((k_iter<T, false, false>), dim3(a.grid_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y, g, cur, perm,
-                                                       v_out, C_out);
+    APIC_GROUP_DISPATCH(L_ITER, false);
+#undef L_ITER
 }
 
 #define INST(T)                                                                                 \

@@ -301,3 +301,29 @@ def random_blobs(seed: int, n_bodies: int = 2, side: int = 5, h: float = 1.0,
         parts.append((pts, v, C, rng.uniform(0.5, 1.5, size=n),
                       np.full(n, bid, dtype=np.uint16)))
     return _assemble(parts, h, name="blobs")
+
+
+def pack(scs, dtype=np.float32):
+    """Concatenate scenes into packed SoA arrays (x, v, C, m, body) of the
+    given float type, with the scene table (list of dicts) and per-scene dt.
+    Pure data movement: the values are the scenes' own, rounded to dtype."""
+    n = sum(sc.n for sc in scs)
+    x = np.empty((3, n), dtype)
+    v = np.empty((3, n), dtype)
+    C = np.empty((9, n), dtype)
+    m = np.empty(n, dtype)
+    body = np.empty(n, np.uint16)
+    table, dts = [], []
+    off = 0
+    for sc in scs:
+        sl = slice(off, off + sc.n)
+        x[:, sl] = sc.x
+        v[:, sl] = sc.v
+        C[:, sl] = sc.C
+        m[sl] = sc.m
+        body[sl] = sc.body
+        table.append(dict(offset=off, count=sc.n, h=sc.h, origin=sc.origin, dims=sc.dims,
+                          mu=sc.mu, n_iter=sc.n_iter, n_bodies=sc.n_bodies))
+        dts.append(sc.dt)
+        off += sc.n
+    return x, v, C, m, body, table, dts

@@ -578,3 +578,23 @@ def test_cell_keys_sort_properties():
     assert np.all(np.diff(perm.astype(np.int64))[ties] > 0)
     # body-major order: bodies appear in increasing id order
     assert np.all(np.diff(sc.body[perm].astype(np.int64)) >= 0)
+
+
+def test_cell_keys_group_cells_blocks_and_super_blocks():
+    """In sorted order every (body, cell), every (body, 4x4x4 block) and every
+    (body, 2x2x2-block super block) forms one contiguous run -- checked from the
+    positions alone, not from the key formula."""
+    sc = scenes.random_blobs(121, n_bodies=3, side=9, h=0.5, jitter_frac=0.45)
+    origin = (-1.3, 0.2, 0.0)
+    grid = ora.Grid(h=sc.h, origin=origin)
+    keys, perm = ora.cell_keys([ora.Scene(0, sc.n, grid, 3)], sc.x, sc.body)
+    cells = np.floor((sc.x[:, perm] - np.array(origin).reshape(3, 1)) / sc.h).astype(np.int64)
+    b = sc.body[perm].astype(np.int64)
+    for div in (1, 4, 8):
+        groups = [tuple(r) for r in np.column_stack([b, np.floor_divide(cells, div).T])]
+        seen, prev = set(), None
+        for g in groups:
+            if g != prev:
+                assert g not in seen, f"group {g} split (division {div})"
+                seen.add(g)
+                prev = g

@@ -223,3 +223,58 @@ def test_full_size_slab_block(ctx, dtype, tol):
     err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
     say(f"  parity error {err:.3e}, blocks {rep['grid_blocks']}")
     assert err <= tol
+
+
+TUNINGS = [dict(item_waves_per_cu=w, node_wg_per_cu=nw, xcd_split=x, p2g_group=g)
+           for (w, nw, x, g) in ((16, 8, 0, 1), (16, 8, 1, 1), (16, 8, 0, 4), (24, 4, 1, 4),
+                                 (16, 8, 0, 8), (8, 32, 1, 8), (1, 1, 0, 8))]
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, FP64_TOL), (np.float32, FP32_TOL)],
+                         ids=["fp64", "fp32"])
+def test_every_launch_tuning_matches_oracle(ctx, dtype, tol):
+    """Each launch tuning (waves per CU, XCD split, 1/4/8 work items merged per
+    workgroup) gives the oracle's result; crowded and sparse cell blocks mix
+    so that runs of many items and single-item runs both occur."""
+    say("tunings", dtype.__name__)
+    sc = scenes.random_blobs(41, n_bodies=3, side=9, h=0.5, spacing_frac=0.45, jitter_frac=0.3)
+    x, v, C, m = cast_inputs(sc, dtype)
+    ref = oracle_step(sc, x, v, C, m, 0.35, 3)
+    for t in TUNINGS:
+        ctx.set_tuning(dtype, sc.n, t)
+        vg, Cg, _ = gpu_step(ctx, sc, x, v, C, m, 0.35, 3)
+        err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
+        say(f"  {t}: {err:.2e}")
+        assert err <= tol
+    ctx.set_tuning(dtype, sc.n, dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=0,
+                                     p2g_group=4))
+
+
+def test_set_tuning_rejects_bad_values(ctx):
+    from paper_2108_02259_amd._lib import ApicError
+    for bad in (dict(item_waves_per_cu=0, node_wg_per_cu=8, xcd_split=0, p2g_group=8),
+                dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=2, p2g_group=8),
+                dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=0, p2g_group=3)):
+        with pytest.raises(ApicError):
+            ctx.set_tuning(np.float32, 1000, bad)
+
+
+def test_autotune_reads_inputs_only_and_keeps_best(ctx):
+    say("autotune")
+    import torch
+    sc = scenes.random_blobs(42, n_bodies=2, side=12, h=1.0)
+    x, v, C, m = cast_inputs(sc, np.float32)
+    dev = torch.device("cuda:0")
+    xt, vt, Ct, mt = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (x, v, C, m))
+    bt = torch.from_numpy(sc.body.view(np.int16).copy()).to(dev)
+    table = [dict(offset=0, count=sc.n, h=sc.h, mu=0.3, n_iter=2, n_bodies=sc.n_bodies)]
+    best, tried = ctx.autotune(table, xt, vt, Ct, mt, bt, reps=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(vt.cpu().numpy(), v) and np.array_equal(Ct.cpu().numpy(), C)
+    assert len(tried) >= 20 and all(ms > 0 for _, ms in tried)
+    times = [ms for _, ms in tried]
+    assert tried[int(np.argmin(times))][0] == best
+    assert ctx.get_tuning(np.float32, sc.n) == best
+    ref = oracle_step(sc, x, v, C, m, 0.3, 2)
+    vg, Cg, _ = gpu_step(ctx, sc, x, v, C, m, 0.3, 2)
+    assert parity_error(vg, Cg, ref["v"], ref["C"], sc.h) <= FP32_TOL
