@@ -263,6 +263,63 @@ apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
                           apic_tuning *candidates, double *times_ms, int32_t max_candidates,
                           int32_t *n_tried);
 
+/* ------------------------------------------------------------------------
+ * Serving loop (continuous batching).
+ *
+ * A server keeps the state of many independent requests resident in one
+ * packed device arena and advances all of them together, one driver step per
+ * tick: the contact step (as apic_contact_step_batched, every resident
+ * request being one scene) and then x <- x + dt v, with each request's own
+ * mu, N and dt.  Requests wait in FIFO order until the arena has room for
+ * their particles, a scene slot is free and the summed apic_scene_footprint of
+ * the resident requests stays within the server's budget; they join at the
+ * next tick and leave once they have taken their steps, their final x, v, C
+ * copied to the caller's output arrays.  A request's result does not depend
+ * on which other requests share its ticks (up to floating-point summation
+ * order).
+ * ------------------------------------------------------------------------ */
+typedef struct apic_server apic_server;
+
+typedef struct {
+  int32_t resident;   /* requests stepped by this tick */
+  int32_t admitted;   /* requests that joined at this tick */
+  int32_t completed;  /* requests that finished at this tick */
+  int32_t queued;     /* requests still waiting after this tick */
+  int64_t particles;  /* particles stepped by this tick */
+  int64_t footprint;  /* summed footprint of the requests stepped by this tick */
+} apic_tick;
+
+/* Create a server on ctx's device: an arena for max_particles resident
+ * particles (device memory allocated here, 2 copies of x, v, C, m, body),
+ * at most max_scenes resident requests, and budget_bytes bounding the summed
+ * footprint of resident requests (0 = no bound). */
+apic_status apic_server_create(apic_ctx *ctx, apic_precision prec, int64_t max_particles,
+                               int32_t max_scenes, int64_t budget_bytes, apic_server **out);
+
+/* Queue a request: one scene (scene->count = its n particles, offset
+ * ignored; grid, mu, n_iter, n_bodies as for a batch) advanced `steps` >= 1
+ * driver steps of `dt`.  x, v, C, m, body_id are device arrays of the request
+ * in the library layout (stride n); they are read when the request is
+ * admitted and must stay valid until then.  x_out, v_out, C_out (device,
+ * stride n) receive the final state and may alias x, v, C.  Returns
+ * APIC_E_BUDGET if the request can never be admitted (more particles than the
+ * arena, or a footprint above the budget). */
+apic_status apic_server_submit(apic_server *srv, int64_t tag, const apic_scene *scene, double dt,
+                               int32_t steps, const void *x, const void *v, const void *C,
+                               const void *m, const uint16_t *body_id, void *x_out, void *v_out,
+                               void *C_out);
+
+/* One tick on `stream`: admit what fits, step every resident request once,
+ * copy out and retire the requests that have taken all their steps, and
+ * synchronise the stream.  info (host, optional) describes the tick;
+ * done_tags (host, optional, max_done entries) receives the tags of the
+ * requests completed by this tick (all of them are retired either way). */
+apic_status apic_server_tick(apic_server *srv, void *stream, apic_tick *info, int64_t *done_tags,
+                             int32_t max_done);
+
+/* Release the server and its arena (queued requests are dropped). */
+void apic_server_destroy(apic_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,12 @@ class Tuning(ctypes.Structure):
                 ("xcd_split", ctypes.c_int32), ("p2g_group", ctypes.c_int32)]
 
 
+class Tick(ctypes.Structure):
+    _fields_ = [("resident", ctypes.c_int32), ("admitted", ctypes.c_int32),
+                ("completed", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("particles", ctypes.c_int64), ("footprint", ctypes.c_int64)]
+
+
 # (name, restype, argtypes) of every exported entry point
 P = ctypes.c_void_p
 SIGNATURES = {
@@ -75,6 +81,13 @@ SIGNATURES = {
     "apic_sim_kernel_times": (ctypes.c_int, [P, P, P]),
     "apic_sim_info": (ctypes.c_int, [P, P]),
     "apic_sim_destroy": (None, [P]),
+    "apic_server_create": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int64, ctypes.POINTER(P)]),
+    "apic_server_submit": (ctypes.c_int, [P, ctypes.c_int64, ctypes.POINTER(Scene), ctypes.c_double,
+                                          ctypes.c_int32, P, P, P, P, P, P, P, P]),
+    "apic_server_tick": (ctypes.c_int, [P, P, ctypes.POINTER(Tick),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "apic_server_destroy": (None, [P]),
     "apic_get_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
     "apic_set_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
     "apic_autotune": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32, ctypes.c_int64,

@@ -234,3 +234,61 @@ class Sim:
 
 def footprint(n: int, blocks_hint: int = 0, precision: int = _lib.FP32_MIXED) -> int:
     return int(lib().apic_scene_footprint(int(n), int(blocks_hint), int(precision)))
+
+
+class Server:
+    """Continuous-batching request loop (apic_server_*): requests join as
+    arena room, scene slots and the footprint budget allow, all resident
+    requests advance one driver step per tick, and finished ones are copied
+    to their output tensors."""
+
+    def __init__(self, ctx: Context, dtype, max_particles: int, max_scenes: int,
+                 budget_bytes: int = 0):
+        self._h = ctypes.c_void_p()
+        self._ctx = ctx
+        self.prec = _prec_of_dtype(dtype)
+        self._keep = {}  # tag -> tensors that must outlive the request
+        check(lib().apic_server_create(ctx._h, self.prec, int(max_particles), int(max_scenes),
+                                       int(budget_bytes), ctypes.byref(self._h)),
+              "apic_server_create")
+        self._done = (ctypes.c_int64 * 4096)()
+
+    def submit(self, tag: int, scene: dict, dt: float, steps: int, x, v, C, m, body,
+               x_out, v_out, C_out):
+        n = _check_tensors(x, v, C, m, body)
+        for name, t, shape in (("x_out", x_out, (3, n)), ("v_out", v_out, (3, n)),
+                               ("C_out", C_out, (9, n))):
+            if tuple(t.shape) != shape or t.dtype != x.dtype or not t.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous {x.dtype} tensor {shape}")
+        if precision_of(x) != self.prec:
+            raise TypeError("request dtype differs from the server's")
+        sc = scene_table([dict(scene, offset=0, count=n)])
+        rc = lib().apic_server_submit(self._h, int(tag), sc, float(dt), int(steps), _ptr(x),
+                                      _ptr(v), _ptr(C), _ptr(m), _ptr(body), _ptr(x_out),
+                                      _ptr(v_out), _ptr(C_out))
+        check(rc, "apic_server_submit")
+        self._keep[int(tag)] = (x, v, C, m, body, x_out, v_out, C_out)
+
+    def tick(self):
+        """One tick; returns (info dict, [completed tags])."""
+        t = _lib.Tick()
+        check(lib().apic_server_tick(self._h, _stream(), ctypes.byref(t), self._done,
+                                     len(self._done)), "apic_server_tick")
+        done = [int(self._done[i]) for i in range(min(t.completed, len(self._done)))]
+        for tag in done:
+            self._keep.pop(tag, None)
+        info = {"resident": t.resident, "admitted": t.admitted, "completed": t.completed,
+                "queued": t.queued, "particles": t.particles, "footprint": t.footprint}
+        return info, done
+
+    def close(self):
+        if self._h:
+            lib().apic_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

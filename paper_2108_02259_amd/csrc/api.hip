@@ -11,19 +11,6 @@
 
 using namespace apic;
 
-#define HIPOK(expr)                                   \
-  do {                                                \
-    if ((expr) != hipSuccess) {                       \
-      (void)hipGetLastError();                        \
-      return APIC_E_DEVICE;                           \
-    }                                                 \
-  } while (0)
-
-#define TRY(expr)                       \
-  do {                                  \
-    apic_status _s = (expr);            \
-    if (_s != APIC_OK) return _s;       \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // workspace

@@ -12,6 +12,20 @@
 #include "apic_internal.h"
 #include "kernels.h"
 
+#define HIPOK(expr)                                   \
+  do {                                                \
+    if ((expr) != hipSuccess) {                       \
+      (void)hipGetLastError();                        \
+      return APIC_E_DEVICE;                           \
+    }                                                 \
+  } while (0)
+
+#define TRY(expr)                       \
+  do {                                  \
+    apic_status _s = (expr);            \
+    if (_s != APIC_OK) return _s;       \
+  } while (0)
+
 namespace apic {
 
 enum BufId {
