@@ -50,7 +50,7 @@ def log(*a):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("transfer.hip", "apic_internal.h"):
+    for f in ("transfer.hip", "layout.hip", "apic_internal.h"):
         with open(os.path.join(ROOT, "paper_2108_02259_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -80,6 +80,62 @@ def cpu_model():
     return platform.processor()
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def serve(ctx, pool, lam, duration, steps, seed, max_particles, max_scenes, budget):
+    """Poisson arrivals at rate lam for `duration` seconds of wall time; each
+    arrival is a request for `steps` driver steps of a pool scene.  Every
+    tick steps all resident requests once; a request's step latency is the
+    duration of the tick that stepped it."""
+    import numpy as np
+    import torch
+    from paper_2108_02259_amd.contact import Server
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / lam, size=int(lam * duration * 2) + 16)
+    t_arr = np.cumsum(gaps)
+    t_arr = t_arr[t_arr < duration]
+    which = rng.integers(0, len(pool), size=len(t_arr))
+    srv = Server(ctx, torch.float32, max_particles, max_scenes, budget)
+    step_lat, req_lat, arrive = [], [], {}
+    stepped = 0
+    ticks = 0
+    i = 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        if now >= duration:
+            break
+        while i < len(t_arr) and t_arr[i] <= now:
+            e = pool[which[i]]
+            srv.submit(i, e["row"], e["dt"], steps, *e["ins"], e["body"], *e["outs"])
+            arrive[i] = t_arr[i]
+            i += 1
+        ts = time.perf_counter()
+        info, done = srv.tick()
+        te = time.perf_counter()
+        if info["resident"] == 0:
+            if i < len(t_arr):
+                time.sleep(max(0.0, min(t_arr[i] - (te - t0), duration - (te - t0))))
+            continue
+        ticks += 1
+        step_lat += [te - ts] * info["resident"]
+        stepped += info["particles"]
+        for tag in done:
+            req_lat.append(te - t0 - arrive.pop(tag))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    srv.close()
+    return {"lambda_per_s": lam, "duration_s": duration, "arrived": int(i),
+            "completed": len(req_lat), "ticks": ticks, "value": stepped / wall,
+            "unit": "particle-steps/s",
+            "p50_step_ms": None if not step_lat else 1e3 * percentile(step_lat, 50),
+            "p99_step_ms": None if not step_lat else 1e3 * percentile(step_lat, 99),
+            "p50_request_s": percentile(req_lat, 50), "p99_request_s": percentile(req_lat, 99)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,10 +146,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch tuning")
     ap.add_argument("--free-flight-steps", type=int, default=50,
                     help="steps of the moving driver (physical dt) reported beside the headline")
     ap.add_argument("--batched-steps", type=int, default=50,
                     help="steps of the 1,024-scene batched form (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="wall time of each serving run (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -131,10 +190,31 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    # ---- FP32-mixed: headline (graph replay) ----------------------------
     use_graph = not args.no_graph
-    sim = make(np.float32)
-    sim.step(args.warmup, graph=use_graph)
+
+    def warmed(dtype):
+        """A sim of this scene warmed up for args.warmup steps (the slab's
+        velocity field has spread, so no node is skipped as zero), autotuned
+        on that state and rebuilt from it with the tuning found."""
+        s0 = make(dtype)
+        s0.step(args.warmup, graph=use_graph)
+        x, v, C = s0.read()
+        s0.close()
+        m = torch.from_numpy(np.ascontiguousarray(sc.m.astype(dtype))).to(dev)
+        tune = None
+        if not args.no_tune:
+            best, tried = ctx.autotune(table, x, v, C, m, bt, reps=2)
+            tune = {"best": best, "best_ms": min(ms for _, ms in tried),
+                    "candidates": len(tried)}
+            log(f"autotune {np.dtype(dtype).name}: {best} "
+                f"({tune['best_ms']:.3f} ms of kernels per step)")
+        s1 = Sim(ctx, table, [0.0], x, v, C, m, bt)
+        s1.step(2, graph=use_graph)
+        return s1, tune
+
+    tuned = {}
+    # ---- FP32-mixed: headline (graph replay) ----------------------------
+    sim, tuned["float32"] = warmed(np.float32)
     t = timed(sim, args.steps, use_graph)
     value = n * args.steps / t
     ms_per_step = 1e3 * t / args.steps
@@ -161,13 +241,14 @@ def main():
     nodes = info["shared_blocks"] * 64
     alg_bytes = n * ROUND_BYTES_PER_PARTICLE["fp32"] + nodes * ROUND_BYTES_PER_NODE["fp32"]
     achieved = alg_bytes / (round_us * 1e-6) / 1e9
-    traffic = traffic_from_profiles("apic::k_iter<float, false, false>")
+    group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
+    round_kernel = f"apic::k_iter<float, false, false, {group}>"
+    traffic = traffic_from_profiles(round_kernel)
     max_drift = drift[0]
     sim.close()
 
     # ---- plain FP64 on the same scene --------------------------------------
-    sim64 = make(np.float64)
-    sim64.step(max(2, args.warmup // 4), graph=use_graph)
+    sim64, tuned["float64"] = warmed(np.float64)
     t64 = timed(sim64, args.fp64_steps, use_graph)
     value64 = n * args.fp64_steps / t64
     _, drift64, _ = sim64.report()
@@ -177,32 +258,78 @@ def main():
     # ---- batched form: 1,024 independent two-body scenes in one set of
     # launches per phase, FP32-mixed, graph replay, each scene at its own dt --
     batched = None
+    batched_moving = None
     if args.batched_steps > 0:
         t0 = time.perf_counter()
         scs = scenes.batch_scenes()
         bx, bv, bC, bm, bb, btable, bdts = scenes.pack(scs, np.float32)
-        log(f"batched: {len(scs)} scenes, {bx.shape[1]} particles (built in "
+        nb = bx.shape[1]
+        log(f"batched: {len(scs)} scenes, {nb} particles (built in "
             f"{time.perf_counter() - t0:.1f} s)")
         arrs = [torch.from_numpy(a).to(dev) for a in (bx, bv, bC, bm)]
         bbt = torch.from_numpy(bb.view(np.int16)).to(dev)
-        simb = Sim(ctx, btable, bdts, *arrs, bbt)
+        btune = None
+        if not args.no_tune:
+            best, tried = ctx.autotune(btable, *arrs, bbt, reps=1)
+            btune = {"best": best, "best_ms": min(ms for _, ms in tried),
+                     "candidates": len(tried)}
+            log(f"autotune batched: {best}")
+            for bucket in range(14, 27):  # the serving loop's tick sizes
+                ctx.set_tuning(torch.float32, 1 << bucket, best)
+
+        def run_batch(dts, label):
+            simb = Sim(ctx, btable, dts, *arrs, bbt)
+            simb.step(2, graph=use_graph)
+            tb = timed(simb, args.batched_steps, use_graph)
+            _, bdrift, _ = simb.report()
+            binfo = simb.info()
+            simb.close()
+            r = {"scenes": len(scs), "particles": nb, "steps": args.batched_steps,
+                 "value": nb * args.batched_steps / tb, "unit": "particle-steps/s",
+                 "ms_per_step": 1e3 * tb / args.batched_steps, "dtype": "fp32-mixed",
+                 "graph": use_graph, "tuning": btune,
+                 "max_drift_P": max(d[0] for d in bdrift),
+                 "max_drift_L": max(d[1] for d in bdrift), "plan": binfo}
+            log(f"batched ({label}): {r['ms_per_step']:.2f} ms/step, {r['value']:.3e} "
+                f"particle-steps/s")
+            return r
+
+        batched = run_batch([0.0] * len(scs), "geometry held")
+        batched["dt"] = "0 (geometry held at the initial configuration)"
+        batched_moving = run_batch(bdts, "moving")
+        batched_moving["dt"] = "per scene, 0.2h / body speed"
         del arrs, bbt
-        simb.step(2, graph=use_graph)
-        tb = timed(simb, args.batched_steps, use_graph)
-        nb = bx.shape[1]
-        _, bdrift, _ = simb.report()
-        binfo = simb.info()
-        simb.close()
-        del simb
         torch.cuda.empty_cache()
-        batched = {"scenes": len(scs), "particles": nb, "steps": args.batched_steps,
-                   "value": nb * args.batched_steps / tb, "unit": "particle-steps/s",
-                   "ms_per_step": 1e3 * tb / args.batched_steps, "dtype": "fp32-mixed",
-                   "graph": use_graph, "dt": "per scene, 0.2h / body speed (moving driver)",
-                   "max_drift_P": max(d[0] for d in bdrift),
-                   "max_drift_L": max(d[1] for d in bdrift), "plan": binfo}
-        log(f"batched: {batched['ms_per_step']:.2f} ms/step, {batched['value']:.3e} "
-            f"particle-steps/s")
+
+    # ---- serving: Poisson request streams, continuous batching -------------
+    serving = None
+    if args.serve_seconds > 0:
+        t0 = time.perf_counter()
+        reqs = scenes.request_stream(lam=1.0, duration=1e9, max_requests=32)
+        pool = []
+        for r in reqs:
+            sc_r = r.scene
+            ins = [torch.from_numpy(np.ascontiguousarray(a.astype(np.float32))).to(dev)
+                   for a in (sc_r.x, sc_r.v, sc_r.C, sc_r.m)]
+            pool.append({"row": dict(h=sc_r.h, origin=sc_r.origin, dims=sc_r.dims, mu=sc_r.mu,
+                                     n_iter=sc_r.n_iter, n_bodies=sc_r.n_bodies),
+                         "dt": sc_r.dt, "ins": ins,
+                         "body": torch.from_numpy(sc_r.body.view(np.int16).copy()).to(dev),
+                         "outs": [torch.empty_like(ins[0]), torch.empty_like(ins[1]),
+                                  torch.empty_like(ins[2])]})
+        log(f"serving pool: {len(pool)} scenes, {sum(r.scene.n for r in reqs)} particles "
+            f"({time.perf_counter() - t0:.1f} s)")
+        cfg = dict(max_particles=32_000_000, max_scenes=512, budget=16 << 30)
+        serve(ctx, pool, 5000.0, min(1.0, args.serve_seconds), 50, 99, **cfg)  # warm-up
+        serving = []
+        for k, lam in enumerate((200.0, 1000.0, 5000.0)):
+            r = serve(ctx, pool, lam, args.serve_seconds, 50, 100 + k, **cfg)
+            log(f"serving lambda {lam:.0f}/s: {r['value']:.3e} particle-steps/s, step p50 "
+                f"{r['p50_step_ms']:.2f} ms p99 {r['p99_step_ms']:.2f} ms, "
+                f"{r['completed']}/{r['arrived']} requests done")
+            serving.append(r)
+        del pool
+        torch.cuda.empty_cache()
 
     # ---- free flight at the scene's time step (cost drifts with occupancy) --
     free = None
@@ -269,14 +396,17 @@ def main():
                    "mu": sc.mu, "n_iter": sc.n_iter, "graph": use_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "apic::k_iter<float, false, false> (fused G2P + rule + P2G round)",
+                     "kernel": round_kernel + " (fused G2P + rule + P2G round)",
                      "kernel_us": round_us, "alg_bytes_per_launch": alg_bytes,
                      "active_nodes": nodes},
         "cpu_baseline": cpu,
         "fp64": {"value": value64, "unit": "particle-steps/s",
                  "ms_per_step": 1e3 * t64 / args.fp64_steps, "steps": args.fp64_steps,
                  "max_drift_P": drift64[0][0], "max_drift_L": drift64[0][1]},
+        "tuning": tuned,
         "batched": batched,
+        "batched_moving": batched_moving,
+        "serving": serving,
         "free_flight": free,
         "max_drift_P": max_drift[0],
         "max_drift_L": max_drift[1],

@@ -207,8 +207,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
   P.seg_cap = std::max<int64_t>(n, 1);
   // items: at most one per particle plus one per 64, plus the run padding
-  // (fewer than kRunAlign per run, one run per super block of a body, and a
-  // body's super blocks number kRunAlign block keys each)
+  // (fewer than the group size per run, one run per super block of a body,
+  // and a body's super blocks number 8 block keys each)
   P.item_cap = n + n / kItem + 1 + kb;
   P.sblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.smap_cap, 8 * n));
   P.bblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.bmap_cap, 8 * n));
@@ -329,7 +329,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
   launch_segments(P.keys, n, P.flags, P.partial, P.tot, P.sbody, P.blay, P.seg, P.seg_cap,
-                  P.items, P.item_cap, P.segtmp, P.cnt, st);
+                  P.items, P.item_cap, P.segtmp, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smap, P.smap_cap, P.bmap, P.bmap_cap,
               P.partial, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
   fill_zero_f(P.g.mass, P.sblk_cap, &P.cnt->n_sblocks, kNodesPerBlock, sizeof(T), st);

@@ -105,9 +105,8 @@ struct Segment {
 
 // A work item: up to kItem particles of one segment.  The items of one
 // (body, super block) run are consecutive and padded with empty items
-// (count 0) to a multiple of kRunAlign, so that aligned groups of 1, 4 or 8
-// items never straddle two runs.
-constexpr int kRunAlign = 8;
+// (count 0) to a multiple of the step's group size, so that aligned groups
+// of 1, 4 or 8 items never straddle two runs.
 struct Item {
   int32_t seg, start, count, pad;
 };

@@ -65,7 +65,7 @@ void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, cons
 void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay,
                      Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,
-                     int32_t *seg_tmp, Counters *cnt, hipStream_t st);
+                     int32_t *seg_tmp, int align, Counters *cnt, hipStream_t st);
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
                  int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,

@@ -613,7 +613,7 @@ __device__ __forceinline__ int32_t seg_items(const Segment *seg, int64_t k, int6
 // Particle count and item count of every segment; the last segment of a run
 // also takes the run's padding items.
 __global__ void k_seg_counts(Segment *seg, int64_t seg_cap, const int64_t *nseg_dev, int64_t n,
-                             int32_t *nitems, Counters *cnt) {
+                             int align, int32_t *nitems, Counters *cnt) {
   int64_t ns = *nseg_dev;
   if (ns > seg_cap) ns = seg_cap;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
@@ -622,11 +622,11 @@ __global__ void k_seg_counts(Segment *seg, int64_t seg_cap, const int64_t *nseg_
     int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
     seg[k].count = (int32_t)(end - sk.start);
     int32_t items = seg_items(seg, k, ns, n);
-    if (k + 1 == ns || !same_run(seg[k + 1], sk)) {
+    if (align > 1 && (k + 1 == ns || !same_run(seg[k + 1], sk))) {
       int32_t run = items;
-      for (int64_t h = k - 1; h >= 0 && k - h < kRunAlign && same_run(seg[h], sk); --h)
+      for (int64_t h = k - 1; h >= 0 && k - h < 8 && same_run(seg[h], sk); --h)
         run += seg_items(seg, h, ns, n);
-      items += (kRunAlign - run % kRunAlign) % kRunAlign;
+      items += (align - run % align) % align;
     }
     nitems[k] = items;
   }
@@ -667,7 +667,7 @@ __global__ void k_items(const Segment *seg, int64_t seg_cap, const int64_t *nseg
 void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay, Segment *seg,
                      int64_t seg_cap, Item *items, int64_t item_cap, int32_t *seg_tmp,
-                     Counters *cnt, hipStream_t st) {
+                     int align, Counters *cnt, hipStream_t st) {
   if (n <= 0) return;
   unsigned g = (unsigned)((n + 255) / 256);
   if (g > 8192) g = 8192;
@@ -676,7 +676,7 @@ void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *p
   APIC_LAUNCH(k_seg_heads, dim3(g), dim3(256), 0, st, keys, n, flags, sbody, blay, seg, seg_cap, cnt);
   unsigned gs = (unsigned)((seg_cap + 255) / 256);
   if (gs > 8192) gs = 8192;
-  APIC_LAUNCH(k_seg_counts, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], n, seg_tmp, cnt);
+  APIC_LAUNCH(k_seg_counts, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], n, align, seg_tmp, cnt);
   scan_exclusive(seg_tmp, seg_tmp, seg_cap, &tot[0], &tot[1], partial, 0, st);
   APIC_LAUNCH(k_items, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], seg_tmp, items, item_cap, cnt, &tot[1]);
 }
