@@ -146,7 +146,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch tuning")
+    ap.add_argument("--tune", choices=("cache", "auto", "off"), default="cache",
+                    help="launch tuning: the committed autotuner cache (autotuning what it "
+                         "lacks), a fresh autotune of every workload, or the defaults")
     ap.add_argument("--free-flight-steps", type=int, default=50,
                     help="steps of the moving driver (physical dt) reported beside the headline")
     ap.add_argument("--batched-steps", type=int, default=50,
@@ -176,6 +178,18 @@ def main():
     table = [dict(offset=0, count=n, h=sc.h, origin=sc.origin, dims=sc.dims, mu=sc.mu,
                   n_iter=sc.n_iter, n_bodies=sc.n_bodies)]
     ctx = Context(0)
+    cache_path = os.path.join(ROOT, "paper_2108_02259_amd", "tuning_cache.json")
+    cache = ctx.load_tuning_cache(cache_path) if args.tune == "cache" else {}
+    new_cache = {}
+
+    def bucket_of(count):
+        return str(int(count).bit_length() - 1)
+
+    def cached(dtype_name, count):
+        return cache.get(dtype_name, {}).get(bucket_of(count))
+
+    def remember(dtype_name, count, best):
+        new_cache.setdefault(dtype_name, {})[bucket_of(count)] = best
     bt = torch.from_numpy(sc.body.view(np.int16).copy()).to(dev)
 
     def make(dtype, dt=0.0):
@@ -202,12 +216,15 @@ def main():
         s0.close()
         m = torch.from_numpy(np.ascontiguousarray(sc.m.astype(dtype))).to(dev)
         tune = None
-        if not args.no_tune:
+        name = np.dtype(dtype).name
+        if args.tune != "off" and cached(name, n):
+            tune = {"best": cached(name, n), "source": "cache"}
+        elif args.tune != "off":
             best, tried = ctx.autotune(table, x, v, C, m, bt, reps=2)
             tune = {"best": best, "best_ms": min(ms for _, ms in tried),
-                    "candidates": len(tried)}
-            log(f"autotune {np.dtype(dtype).name}: {best} "
-                f"({tune['best_ms']:.3f} ms of kernels per step)")
+                    "candidates": len(tried), "source": "autotune"}
+            remember(name, n, best)
+            log(f"autotune {name}: {best} ({tune['best_ms']:.3f} ms of kernels per step)")
         s1 = Sim(ctx, table, [0.0], x, v, C, m, bt)
         s1.step(2, graph=use_graph)
         return s1, tune
@@ -269,13 +286,17 @@ def main():
         arrs = [torch.from_numpy(a).to(dev) for a in (bx, bv, bC, bm)]
         bbt = torch.from_numpy(bb.view(np.int16)).to(dev)
         btune = None
-        if not args.no_tune:
+        if args.tune != "off" and cached("float32", nb):
+            btune = {"best": cached("float32", nb), "source": "cache"}
+        elif args.tune != "off":
             best, tried = ctx.autotune(btable, *arrs, bbt, reps=1)
             btune = {"best": best, "best_ms": min(ms for _, ms in tried),
-                     "candidates": len(tried)}
+                     "candidates": len(tried), "source": "autotune"}
             log(f"autotune batched: {best}")
-            for bucket in range(14, 27):  # the serving loop's tick sizes
-                ctx.set_tuning(torch.float32, 1 << bucket, best)
+            for bucket in range(14, 27):  # the serving loop's tick sizes too
+                if str(bucket) != bucket_of(n):
+                    ctx.set_tuning(torch.float32, 1 << bucket, best)
+                    new_cache.setdefault("float32", {})[str(bucket)] = best
 
         def run_batch(dts, label):
             simb = Sim(ctx, btable, dts, *arrs, bbt)
@@ -414,6 +435,8 @@ def main():
         "kernels_us": {k: (1e3 * ms / cnt if cnt else None) for k, (ms, cnt) in kt.items()},
         "plan": info,
     }
+    if new_cache:
+        log("tuning cache entries found by the autotuner in this run: " + json.dumps(new_cache))
     print(json.dumps(out), flush=True)
     ctx.close()
 
