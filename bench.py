@@ -12,13 +12,16 @@ The timed steps keep the geometry of the scene's initial configuration
 (driver time step 0: x += 0 * v), so every step does the work of the same
 input.  With a nonzero time step the bodies here have no internal forces:
 the block's particles keep moving into its own contact layer, cell
-occupancy climbs step after step, and the step cost drifts with it.  That
-free-flight rate over the first steps is reported beside the headline.
+occupancy climbs step after step, and the step cost drifts with it
+(--free-flight-steps reports that rate).
 
 Prints ONE JSON line: FP32-mixed throughput (the headline value, graph
 replay), the plain FP64 throughput on the same scene, the roofline of the
 dominant kernel (the fused round kernel, timed with HIP events on its
-stream), and the CPU oracle timed on this host on a bounded sample.
+stream), the batched form (1,024 two-body scenes) and the serving loop
+(Poisson request streams, p50/p99 step latency), and the CPU oracle timed on
+this host on a bounded sample.  Launch tunings come from the committed
+autotuner cache (--tune auto re-tunes).
 """
 from __future__ import annotations
 
@@ -149,8 +152,10 @@ def main():
     ap.add_argument("--tune", choices=("cache", "auto", "off"), default="cache",
                     help="launch tuning: the committed autotuner cache (autotuning what it "
                          "lacks), a fresh autotune of every workload, or the defaults")
-    ap.add_argument("--free-flight-steps", type=int, default=50,
-                    help="steps of the moving driver (physical dt) reported beside the headline")
+    ap.add_argument("--free-flight-steps", type=int, default=0,
+                    help="steps of the moving driver (physical dt) to report beside the "
+                         "headline (its round kernels, slowed by growing cell occupancy, "
+                         "would mix into a profile of the headline kernel)")
     ap.add_argument("--batched-steps", type=int, default=50,
                     help="steps of the 1,024-scene batched form (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
@@ -177,19 +182,30 @@ def main():
     log(f"scene slab_block n={n} mu={sc.mu} N={sc.n_iter} dt={sc.dt:.4f}")
     table = [dict(offset=0, count=n, h=sc.h, origin=sc.origin, dims=sc.dims, mu=sc.mu,
                   n_iter=sc.n_iter, n_bodies=sc.n_bodies)]
+    # Two contexts, each with the launch tuning of its scene class: the slab
+    # scene of the headline, and the two-body scenes of the batched form and
+    # the serving loop (whose tick sizes span many size buckets).
     ctx = Context(0)
+    ctx2 = Context(0)
     cache_path = os.path.join(ROOT, "paper_2108_02259_amd", "tuning_cache.json")
-    cache = ctx.load_tuning_cache(cache_path) if args.tune == "cache" else {}
+    cache = {}
+    if args.tune == "cache" and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    for cls, c in (("slab_block", ctx), ("two_body", ctx2)):
+        for prec, entries in cache.get(cls, {}).items():
+            for b, t in entries.items():
+                c.set_tuning(prec, 1 << int(b), t)
     new_cache = {}
 
     def bucket_of(count):
         return str(int(count).bit_length() - 1)
 
-    def cached(dtype_name, count):
-        return cache.get(dtype_name, {}).get(bucket_of(count))
+    def cached(cls, dtype_name, count):
+        return cache.get(cls, {}).get(dtype_name, {}).get(bucket_of(count))
 
-    def remember(dtype_name, count, best):
-        new_cache.setdefault(dtype_name, {})[bucket_of(count)] = best
+    def remember(cls, dtype_name, count, best):
+        new_cache.setdefault(cls, {}).setdefault(dtype_name, {})[bucket_of(count)] = best
     bt = torch.from_numpy(sc.body.view(np.int16).copy()).to(dev)
 
     def make(dtype, dt=0.0):
@@ -217,13 +233,13 @@ def main():
         m = torch.from_numpy(np.ascontiguousarray(sc.m.astype(dtype))).to(dev)
         tune = None
         name = np.dtype(dtype).name
-        if args.tune != "off" and cached(name, n):
-            tune = {"best": cached(name, n), "source": "cache"}
+        if args.tune != "off" and cached("slab_block", name, n):
+            tune = {"best": cached("slab_block", name, n), "source": "cache"}
         elif args.tune != "off":
             best, tried = ctx.autotune(table, x, v, C, m, bt, reps=2)
             tune = {"best": best, "best_ms": min(ms for _, ms in tried),
                     "candidates": len(tried), "source": "autotune"}
-            remember(name, n, best)
+            remember("slab_block", name, n, best)
             log(f"autotune {name}: {best} ({tune['best_ms']:.3f} ms of kernels per step)")
         s1 = Sim(ctx, table, [0.0], x, v, C, m, bt)
         s1.step(2, graph=use_graph)
@@ -286,20 +302,19 @@ def main():
         arrs = [torch.from_numpy(a).to(dev) for a in (bx, bv, bC, bm)]
         bbt = torch.from_numpy(bb.view(np.int16)).to(dev)
         btune = None
-        if args.tune != "off" and cached("float32", nb):
-            btune = {"best": cached("float32", nb), "source": "cache"}
+        if args.tune != "off" and cached("two_body", "float32", nb):
+            btune = {"best": cached("two_body", "float32", nb), "source": "cache"}
         elif args.tune != "off":
-            best, tried = ctx.autotune(btable, *arrs, bbt, reps=1)
+            best, tried = ctx2.autotune(btable, *arrs, bbt, reps=1)
             btune = {"best": best, "best_ms": min(ms for _, ms in tried),
                      "candidates": len(tried), "source": "autotune"}
             log(f"autotune batched: {best}")
-            for bucket in range(14, 27):  # the serving loop's tick sizes too
-                if str(bucket) != bucket_of(n):
-                    ctx.set_tuning(torch.float32, 1 << bucket, best)
-                    new_cache.setdefault("float32", {})[str(bucket)] = best
+            for bucket in range(10, 27):  # the serving loop's tick sizes too
+                ctx2.set_tuning(torch.float32, 1 << bucket, best)
+                remember("two_body", "float32", 1 << bucket, best)
 
         def run_batch(dts, label):
-            simb = Sim(ctx, btable, dts, *arrs, bbt)
+            simb = Sim(ctx2, btable, dts, *arrs, bbt)
             simb.step(2, graph=use_graph)
             tb = timed(simb, args.batched_steps, use_graph)
             _, bdrift, _ = simb.report()
@@ -341,10 +356,10 @@ def main():
         log(f"serving pool: {len(pool)} scenes, {sum(r.scene.n for r in reqs)} particles "
             f"({time.perf_counter() - t0:.1f} s)")
         cfg = dict(max_particles=32_000_000, max_scenes=512, budget=16 << 30)
-        serve(ctx, pool, 5000.0, min(1.0, args.serve_seconds), 50, 99, **cfg)  # warm-up
+        serve(ctx2, pool, 5000.0, min(1.0, args.serve_seconds), 50, 99, **cfg)  # warm-up
         serving = []
         for k, lam in enumerate((200.0, 1000.0, 5000.0)):
-            r = serve(ctx, pool, lam, args.serve_seconds, 50, 100 + k, **cfg)
+            r = serve(ctx2, pool, lam, args.serve_seconds, 50, 100 + k, **cfg)
             log(f"serving lambda {lam:.0f}/s: {r['value']:.3e} particle-steps/s, step p50 "
                 f"{r['p50_step_ms']:.2f} ms p99 {r['p99_step_ms']:.2f} ms, "
                 f"{r['completed']}/{r['arrived']} requests done")
@@ -438,6 +453,7 @@ def main():
     if new_cache:
         log("tuning cache entries found by the autotuner in this run: " + json.dumps(new_cache))
     print(json.dumps(out), flush=True)
+    ctx2.close()
     ctx.close()
 
 

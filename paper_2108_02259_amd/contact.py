@@ -113,26 +113,6 @@ class Context:
         check(lib().apic_set_tuning(self._h, _prec_of_dtype(dtype), int(n), ctypes.byref(t)),
               "apic_set_tuning")
 
-    def load_tuning_cache(self, path: str) -> dict:
-        """Apply a tuning cache written by save_tuning_cache: {precision:
-        {size bucket: tuning}}.  Returns the cache (empty if no file)."""
-        import json
-        import os
-        if not os.path.exists(path):
-            return {}
-        with open(path) as f:
-            cache = json.load(f)
-        for prec, entries in cache.items():
-            for bucket, t in entries.items():
-                self.set_tuning(prec, 1 << int(bucket), t)
-        return cache
-
-    @staticmethod
-    def save_tuning_cache(path: str, cache: dict):
-        import json
-        with open(path, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
-
     def autotune(self, scenes, x, v, C, m, body, reps: int = 2):
         """Time every candidate launch tuning on this batch (inputs are only
         read) and keep the fastest for its (precision, size bucket).  Returns
