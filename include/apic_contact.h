@@ -133,10 +133,14 @@ apic_status apic_contact_step_batched(apic_ctx *ctx, void *stream,
 /* Cell keys and the stable particle order of a batch (the layout step of the
  * contact step, exposed for verification): keys_sorted[i] is the 32-bit cell
  * key of the i-th particle in sorted order and perm[i] its input index.
- * key = (body block offset + local block, x fastest) * 64 + cell in block,
- * with cells floor((x - origin)/h) in FP64 and 4x4x4-cell blocks; each body's
- * block box is laid out in (scene, body) order.  Equal keys keep input
- * order.  keys_sorted and perm are device arrays of n_total entries. */
+ * key = block number * 64 + cell in block (x fastest), with cells
+ * floor((x - origin)/h) in FP64 and 4x4x4-cell blocks; each body's key range
+ * numbers its blocks super block by super block (2x2x2 blocks, row-major over
+ * the body's super-block box, x fastest, then x fastest within the super
+ * block), bodies in (scene, body) order.  Equal keys keep input order.  (The
+ * contact step itself orders particles by block number only, keeping input
+ * order within a block.)  keys_sorted and perm are device arrays of n_total
+ * entries. */
 apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes,
                            int32_t n_scenes, int64_t n_total, const void *x,
                            const uint16_t *body_id, apic_precision prec,

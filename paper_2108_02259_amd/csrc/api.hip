@@ -35,6 +35,7 @@ apic_status Workspace::ensure(int id, size_t bytes) {
   ptr[id] = p;
   size[id] = bytes;
   held += bytes;
+  fresh[id] = true;
   return APIC_OK;
 }
 
@@ -197,7 +198,8 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
 // Capacities from the sizes of a measured layout (times `headroom`), then
 // every buffer of the step.
 static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t key_blocks,
-                                int64_t smap_total, int64_t bmap_total, double headroom) {
+                                int64_t smap_total, int64_t bmap_total, double headroom,
+                                hipStream_t st) {
   const int64_t n = P.n;
   int64_t kb = std::max<int64_t>(1, (int64_t)std::ceil(key_blocks * headroom));
   int bits = 1;
@@ -236,11 +238,11 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kValsA, sizeof(uint32_t) * n));
   TRY(W.ensure(kKeysB, sizeof(uint32_t) * n));
   TRY(W.ensure(kValsB, sizeof(uint32_t) * n));
-  TRY(W.ensure(kHist, sizeof(uint32_t) * 256 * ntiles));
-  int64_t pcap = std::max(scan_partials_needed(256 * ntiles),
-                          scan_partials_needed(std::max<int64_t>(
-                              {n * 2, P.smap_cap, P.bmap_cap, (int64_t)1})));
-  TRY(W.ensure(kPartial, sizeof(int32_t) * pcap));
+  TRY(W.ensure(kGhist, sizeof(uint32_t) * radix_hist_words(n)));
+  const int64_t lbcap = scan_tile_count(
+      std::max<int64_t>({n, P.seg_cap, P.smap_cap, P.bmap_cap, 256 * ntiles}));
+  TRY(W.ensure(kLbFlags, sizeof(uint64_t) * lbcap));
+  TRY(W.ensure(kLbState, sizeof(uint32_t) * 2));
   TRY(W.ensure(kT, T * 3 * n));
   TRY(W.ensure(kMs, T * n));
   TRY(W.ensure(kSbody, sizeof(int32_t) * n));
@@ -248,9 +250,12 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kY, T * 12 * n));
   TRY(W.ensure(kSeg, sizeof(Segment) * P.seg_cap));
   TRY(W.ensure(kSegTmp, sizeof(int32_t) * (P.seg_cap + 1)));
+  TRY(W.ensure(kItemOff, sizeof(int32_t) * (P.seg_cap + 1)));
   TRY(W.ensure(kFlags, sizeof(int32_t) * n));
   TRY(W.ensure(kItems, sizeof(Item) * P.item_cap));
+  TRY(W.ensure(kSmark, sizeof(int32_t) * P.smap_cap));
   TRY(W.ensure(kSmap, sizeof(int32_t) * P.smap_cap));
+  TRY(W.ensure(kBmark, sizeof(int32_t) * P.bmap_cap));
   TRY(W.ensure(kBmap, sizeof(int32_t) * P.bmap_cap));
   TRY(W.ensure(kGMass, T * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kGBuf0, T * 3 * kNodesPerBlock * P.sblk_cap));
@@ -264,8 +269,13 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.va = (uint32_t *)W.ptr[kValsA];
   P.kb = (uint32_t *)W.ptr[kKeysB];
   P.vb = (uint32_t *)W.ptr[kValsB];
-  P.hist = (uint32_t *)W.ptr[kHist];
-  P.partial = (int32_t *)W.ptr[kPartial];
+  P.ghist = (uint32_t *)W.ptr[kGhist];
+  P.lb.flags = (uint64_t *)W.ptr[kLbFlags];
+  P.lb.capacity = (int64_t)(W.size[kLbFlags] / sizeof(uint64_t));
+  P.lb.state = (uint32_t *)W.ptr[kLbState];
+  P.item_off = (int32_t *)W.ptr[kItemOff];
+  P.smark = (int32_t *)W.ptr[kSmark];
+  P.bmark = (int32_t *)W.ptr[kBmark];
   P.t = W.ptr[kT];
   P.ms = W.ptr[kMs];
   P.sbody = (int32_t *)W.ptr[kSbody];
@@ -281,6 +291,14 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.g.buf[0] = W.ptr[kGBuf0];
   P.g.buf[1] = W.ptr[kGBuf1];
   P.g.bmass = (double *)W.ptr[kBMass];
+  // state that kernels keep between launches starts from zero (mark arrays)
+  // or a fresh look-back epoch whenever its buffer is new
+  if (W.fresh[kLbFlags] || W.fresh[kLbState]) lookback_init(P.lb, st);
+  // (the whole allocation: a later plan may use more of it without growing it)
+  if (W.fresh[kSmark]) fill_bytes_zero(P.smark, (int64_t)W.size[kSmark], st);
+  if (W.fresh[kBmark]) fill_bytes_zero(P.bmark, (int64_t)W.size[kBmark], st);
+  W.fresh[kLbFlags] = W.fresh[kLbState] = false;
+  W.fresh[kSmark] = W.fresh[kBmark] = false;
   P.ready = true;
   return APIC_OK;
 }
@@ -300,14 +318,18 @@ static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *
                  check_caps ? P.bmap_cap : 0, st);
 }
 
-// keys + sort; sets P.keys / P.perm
+// keys + sort; sets P.keys / P.perm.  The contact step needs particles
+// grouped by (scene, body, block) only -- the per-cell pass ranking works in
+// any order within a block -- so it sorts by the block part of the key
+// (bits 6 and up) and keeps input order within a block; full_key sorts by
+// the whole key (the ordering apic_sort_keys returns).
 template <typename T>
 static void enqueue_sort(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
-                         Profiler *prof) {
+                         Profiler *prof, bool full_key = false) {
   launch_keys<T>(x, body, P.n, P.sc, P.ns, P.blay, P.ka, st);
   if (prof) prof->end(APIC_KC_LAYOUT, st), prof->begin(st);
-  int where = radix_sort(P.ka, P.va, P.kb, P.vb, P.n, P.sort_bits, P.hist, P.partial, P.tot + 9,
-                         st);
+  int where = radix_sort(P.ka, P.va, P.kb, P.vb, P.n, full_key ? 0 : 6, P.sort_bits, P.ghist,
+                         P.lb, st);
   if (prof) prof->end(APIC_KC_SORT, st);
   P.keys = where ? P.kb : P.ka;
   P.perm = where ? P.vb : P.va;
@@ -328,10 +350,10 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
                    x_sorted, body_sorted, orig_in, orig_out, P.rec_gather, P.red, st);
   launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
-  launch_segments(P.keys, n, P.flags, P.partial, P.tot, P.sbody, P.blay, P.seg, P.seg_cap,
-                  P.items, P.item_cap, P.segtmp, P.group, P.cnt, st);
-  launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smap, P.smap_cap, P.bmap, P.bmap_cap,
-              P.partial, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
+  launch_segments(P.keys, n, P.flags, P.lb, P.tot, P.sbody, P.blay, P.seg, P.seg_cap, P.items,
+                  P.item_cap, P.segtmp, P.item_off, P.group, P.cnt, st);
+  launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
+              P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
   fill_zero_f(P.g.mass, P.sblk_cap, &P.cnt->n_sblocks, kNodesPerBlock, sizeof(T), st);
   fill_zero_f(P.g.buf[0], P.sblk_cap, &P.cnt->n_sblocks, 3 * kNodesPerBlock, sizeof(T), st);
   fill_zero_f(P.g.bmass, P.bblk_cap, &P.cnt->n_bblocks, kNodesPerBlock, sizeof(double), st);
@@ -422,7 +444,7 @@ static apic_status step_impl(apic_ctx *ctx, hipStream_t st, const apic_scene *sc
   HIPOK(hipStreamSynchronize(st));
   std::memcpy(&c, ctx->stage, sizeof(Counters));
   TRY(status_from_err(c.err));
-  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0));
+  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0, st));
   TRY(W.ensure(kVbar, sizeof(T) * 12 * n));
   enqueue_sort<T>(P, st, x, body, nullptr);
   enqueue_body<T>(P, st, x, v, C, m, body, (T *)W.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
@@ -573,7 +595,7 @@ static apic_status sim_plan(apic_sim *S, hipStream_t st, double headroom) {
   HIPOK(hipStreamSynchronize(st));
   std::memcpy(&c, S->ctx->stage, sizeof(Counters));
   TRY(status_from_err(c.err));
-  TRY(plan_buffers(S->ctx, S->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom));
+  TRY(plan_buffers(S->ctx, S->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom, st));
   S->graph_ok = false;
   return APIC_OK;
 }
@@ -711,11 +733,11 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
   HIPOK(hipStreamSynchronize(st));
   std::memcpy(&c, ctx->stage, sizeof(Counters));
   TRY(status_from_err(c.err));
-  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0));
+  TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0, st));
   if (prec == APIC_FP64)
-    enqueue_sort<double>(P, st, (const double *)x, body_id, nullptr);
+    enqueue_sort<double>(P, st, (const double *)x, body_id, nullptr, true);
   else
-    enqueue_sort<float>(P, st, (const float *)x, body_id, nullptr);
+    enqueue_sort<float>(P, st, (const float *)x, body_id, nullptr, true);
   HIPOK(hipMemcpyAsync(keys_sorted, P.keys, sizeof(uint32_t) * n_total, hipMemcpyDeviceToDevice,
                        st));
   HIPOK(hipMemcpyAsync(perm, P.perm, sizeof(uint32_t) * n_total, hipMemcpyDeviceToDevice, st));

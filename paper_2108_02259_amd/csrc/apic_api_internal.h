@@ -30,14 +30,16 @@ namespace apic {
 
 enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
-  kValsB, kHist, kPartial, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
-  kFlags, kItems, kSmap, kBmap, kGMass, kGBuf0, kGBuf1, kBMass, kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
+  kValsB, kGhist, kLbFlags, kLbState, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
+  kItemOff, kFlags, kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kBMass,
+  kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
 };
 
 // Grow-only device buffers, bounded by an HBM budget.
 struct Workspace {
   void *ptr[kNumBufs] = {};
   size_t size[kNumBufs] = {};
+  bool fresh[kNumBufs] = {};  // (re)allocated since the caller last cleared it
   size_t held = 0;
   size_t budget = 0;
   apic_status ensure(int id, size_t bytes);
@@ -71,15 +73,15 @@ struct Plan {
   double *red = nullptr;
   BoxRec *box_rec = nullptr;
   RedRec *rec_gather = nullptr, *rec_items = nullptr;
-  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr;
-  int32_t *partial = nullptr;
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *ghist = nullptr;
+  Lookback lb = {};
   uint32_t *keys = nullptr, *perm = nullptr;
   void *t = nullptr, *ms = nullptr, *nrm = nullptr, *Y = nullptr;
   int32_t *sbody = nullptr;
   Segment *seg = nullptr;
-  int32_t *segtmp = nullptr, *flags = nullptr;
+  int32_t *segtmp = nullptr, *item_off = nullptr, *flags = nullptr;
   Item *items = nullptr;
-  int32_t *smap = nullptr, *bmap = nullptr;
+  int32_t *smark = nullptr, *smap = nullptr, *bmark = nullptr, *bmap = nullptr;
   GridPtrs g = {};
 };
 

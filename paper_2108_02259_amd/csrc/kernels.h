@@ -10,15 +10,29 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-inline int64_t scan_partials_needed(int64_t n_cap) {
+inline int64_t scan_tile_count(int64_t n_cap) {
   return (n_cap + kScanTile - 1) / kScanTile + 1;
 }
 
-// Exclusive prefix sum of in[0, n) into out (may alias in).  n is n_dev[0]
-// when n_dev is non-null (n_cap bounds it), else n_cap.  The total is written
-// to *total (int64).  mode 1 writes -1 where in[i] == 0 (slot maps).
+// Device state of the single-pass scans and sort passes (decoupled
+// look-back): flag words and {finished tiles, epoch}.  Initialise once with
+// lookback_init; launches on one Lookback must not overlap.
+struct Lookback {
+  uint64_t *flags;
+  int64_t capacity;  // flag words: >= tiles of any scan, >= 256 * tiles of any sort pass
+  uint32_t *state;
+};
+void lookback_init(const Lookback &lb, hipStream_t st);
+
+// Exclusive prefix sum of in[0, n) into out (out must not alias in).  n is
+// n_dev[0] when n_dev is non-null (n_cap bounds it), else n_cap.  The total is
+// written to *total (int64).  mode 1 writes -1 where in[i] == 0 (slot maps).
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_t *n_dev,
-                    int64_t *total, int32_t *partial, int mode, hipStream_t st);
+                    int64_t *total, const Lookback &lb, int mode, hipStream_t st);
+// Segment number of every sorted particle (exclusive scan of "a new 4x4x4
+// block starts here" flags, computed from the keys), total segments to *total.
+void scan_segment_heads(const uint32_t *keys, int32_t *seg_id, int64_t n, int64_t *total,
+                        const Lookback &lb, hipStream_t st);
 
 void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, int64_t scale,
               hipStream_t st);
@@ -28,17 +42,21 @@ void fill_zero_f(void *p, int64_t elems_cap, const int32_t *n_dev, int64_t per, 
 
 // ---- radix sort (sort.hip) -------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-// Stable LSD radix sort of (key, index) over the low `bits` key bits, 8 bits
-// per pass.  keys/vals ping-pong between the a and b buffers; the return value
-// is 0 if the result is in (ka, va), 1 if in (kb, vb).  Values start as the
-// identity permutation 0..n-1 (va need not be initialised).
-int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n, int bits,
-               uint32_t *hist, int32_t *partial, int64_t *total, hipStream_t st);
+// Stable LSD radix sort of (key, index) by key bits [lo, bits), 8 bits per
+// pass (at most 4), each pass: per-tile digit counts, a single-pass scan of
+// them in digit-major order, and the scatter.
+// keys/vals ping-pong between the a and b buffers; the return value is 0 if
+// the result is in (ka, va), 1 if in (kb, vb).  Values start as the identity
+// permutation 0..n-1 (va need not be initialised).  hist holds
+// radix_hist_words(n) words of scratch.
+inline int64_t radix_hist_words(int64_t n) { return 2 * 256 * sort_tiles(n) + 4; }
+int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n, int lo,
+               int bits, uint32_t *hist, const Lookback &lb, hipStream_t st);
 
 // ---- layout (layout.hip) ---------------------------------------------------
 // One box record per wavefront (rec has ceil(n/256)*4 entries), then reduced.
@@ -62,14 +80,18 @@ void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, cons
                    T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
                    T *x_out, uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
                    RedRec *rec, double *direct, hipStream_t st);
-void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
+void launch_segments(const uint32_t *keys, int64_t n, int32_t *seg_id, const Lookback &lb,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay,
                      Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,
-                     int32_t *seg_tmp, int align, Counters *cnt, hipStream_t st);
+                     int32_t *seg_tmp, int32_t *item_off, int align, Counters *cnt,
+                     hipStream_t st);
+// Node-block maps: mark the blocks every segment touches, scan the marks into
+// slots, store each segment's 8 slots and clear the marks again (so that the
+// mark arrays are all zero between steps).
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
-                 int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
-                 int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,
-                 int64_t bblk_cap, hipStream_t st);
+                 int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
+                 int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
+                 int64_t sblk_cap, int64_t bblk_cap, hipStream_t st);
 
 // ---- transfers (transfer.hip) ---------------------------------------------
 struct GridPtrs {

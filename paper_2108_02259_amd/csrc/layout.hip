@@ -552,11 +552,6 @@ template void launch_after<double>(int64_t, const uint32_t *, double *, const do
 // ---------------------------------------------------------------------------
 // segments and work items
 // ---------------------------------------------------------------------------
-__global__ void k_seg_flags(const uint32_t *keys, int64_t n, int32_t *flags) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    flags[i] = (i == 0 || (keys[i] >> 6) != (keys[i - 1] >> 6)) ? 1 : 0;
-}
 
 // flags have been scanned in place into seg ids; heads write segments.
 __global__ void k_seg_heads(const uint32_t *keys, int64_t n, const int32_t *segid,
@@ -664,21 +659,20 @@ __global__ void k_items(const Segment *seg, int64_t seg_cap, const int64_t *nseg
   }
 }
 
-void launch_segments(const uint32_t *keys, int64_t n, int32_t *flags, int32_t *partial,
+void launch_segments(const uint32_t *keys, int64_t n, int32_t *seg_id, const Lookback &lb,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay, Segment *seg,
                      int64_t seg_cap, Item *items, int64_t item_cap, int32_t *seg_tmp,
-                     int align, Counters *cnt, hipStream_t st) {
+                     int32_t *item_off, int align, Counters *cnt, hipStream_t st) {
   if (n <= 0) return;
   unsigned g = (unsigned)((n + 255) / 256);
   if (g > 8192) g = 8192;
-  APIC_LAUNCH(k_seg_flags, dim3(g), dim3(256), 0, st, keys, n, flags);
-  scan_exclusive(flags, flags, n, nullptr, &tot[0], partial, 0, st);
-  APIC_LAUNCH(k_seg_heads, dim3(g), dim3(256), 0, st, keys, n, flags, sbody, blay, seg, seg_cap, cnt);
+  scan_segment_heads(keys, seg_id, n, &tot[0], lb, st);
+  APIC_LAUNCH(k_seg_heads, dim3(g), dim3(256), 0, st, keys, n, seg_id, sbody, blay, seg, seg_cap, cnt);
   unsigned gs = (unsigned)((seg_cap + 255) / 256);
   if (gs > 8192) gs = 8192;
   APIC_LAUNCH(k_seg_counts, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], n, align, seg_tmp, cnt);
-  scan_exclusive(seg_tmp, seg_tmp, seg_cap, &tot[0], &tot[1], partial, 0, st);
-  APIC_LAUNCH(k_items, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], seg_tmp, items, item_cap, cnt, &tot[1]);
+  scan_exclusive(seg_tmp, item_off, seg_cap, &tot[0], &tot[1], lb, 0, st);
+  APIC_LAUNCH(k_items, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], item_off, items, item_cap, cnt, &tot[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -695,16 +689,15 @@ __device__ __forceinline__ int64_t bmap_index(const BodyLay &L, int bx, int by, 
   return L.bmap_off + rx + ex * (ry + ey * rz);
 }
 
-__global__ void k_copy_totals(Counters *cnt, int64_t *tot) {
-  tot[5] = cnt->smap_total;
-  tot[6] = cnt->bmap_total;
-}
-
 __global__ void k_mark(const Segment *seg, const Counters *cnt, int64_t seg_cap,
-                       const SceneLay *slay, const BodyLay *blay, int32_t *smap, int64_t smap_cap,
-                       int32_t *bmap, int64_t bmap_cap) {
+                       const SceneLay *slay, const BodyLay *blay, int32_t *smark, int64_t smap_cap,
+                       int32_t *bmark, int64_t bmap_cap, int64_t *tot) {
   int64_t ns = cnt->n_seg;
   if (ns > seg_cap) ns = seg_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tot[5] = cnt->smap_total;
+    tot[6] = cnt->bmap_total;
+  }
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = q >> 3;
@@ -713,14 +706,18 @@ __global__ void k_mark(const Segment *seg, const Counters *cnt, int64_t seg_cap,
     const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
     int64_t si = smap_index(slay[sg.scene], bx, by, bz);
     int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
-    if (si >= 0 && si < smap_cap) smap[si] = 1;
-    if (bi >= 0 && bi < bmap_cap) bmap[bi] = 1;
+    if (si >= 0 && si < smap_cap) smark[si] = 1;
+    if (bi >= 0 && bi < bmap_cap) bmark[bi] = 1;
   }
 }
 
-__global__ void k_seg_slots(Segment *seg, const Counters *cnt, int64_t seg_cap,
-                            const SceneLay *slay, const BodyLay *blay, const int32_t *smap,
-                            int64_t smap_cap, const int32_t *bmap, int64_t bmap_cap) {
+// Each segment's 8 slots; the marks are cleared for the next step, and the
+// first thread turns the slot totals into block counts (with capacity checks).
+__global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const SceneLay *slay,
+                            const BodyLay *blay, int32_t *smark, const int32_t *smap,
+                            int64_t smap_cap, int32_t *bmark, const int32_t *bmap,
+                            int64_t bmap_cap, const int64_t *tot, int64_t sblk_cap,
+                            int64_t bblk_cap) {
   int64_t ns = cnt->n_seg;
   if (ns > seg_cap) ns = seg_cap;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
@@ -731,38 +728,36 @@ __global__ void k_seg_slots(Segment *seg, const Counters *cnt, int64_t seg_cap,
     const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
     int64_t si = smap_index(slay[sg.scene], bx, by, bz);
     int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
-    sg.sslot[j] = (si >= 0 && si < smap_cap) ? smap[si] : -1;
-    sg.bslot[j] = (bi >= 0 && bi < bmap_cap) ? bmap[bi] : -1;
+    const bool sok = si >= 0 && si < smap_cap, bok = bi >= 0 && bi < bmap_cap;
+    sg.sslot[j] = sok ? smap[si] : -1;
+    sg.bslot[j] = bok ? bmap[bi] : -1;
+    if (sok) smark[si] = 0;
+    if (bok) bmark[bi] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t s = tot[2], b = tot[3];
+    int err = 0;
+    if (s > sblk_cap || b > bblk_cap) err |= kErrCapacity;
+    if (cnt->smap_total > smap_cap || cnt->bmap_total > bmap_cap) err |= kErrCapacity;
+    if (err) atomicOr(&cnt->err, err);
+    cnt->n_sblocks = (int32_t)(s < sblk_cap ? s : sblk_cap);
+    cnt->n_bblocks = (int32_t)(b < bblk_cap ? b : bblk_cap);
   }
 }
 
-__global__ void k_block_counts(Counters *cnt, const int64_t *tot, int64_t sblk_cap,
-                               int64_t bblk_cap, int64_t smap_cap, int64_t bmap_cap) {
-  int64_t s = tot[2], b = tot[3];
-  int err = 0;
-  if (s > sblk_cap) err |= kErrCapacity;
-  if (b > bblk_cap) err |= kErrCapacity;
-  if (cnt->smap_total > smap_cap || cnt->bmap_total > bmap_cap) err |= kErrCapacity;
-  if (err) atomicOr(&cnt->err, err);
-  cnt->n_sblocks = (int32_t)(s < sblk_cap ? s : sblk_cap);
-  cnt->n_bblocks = (int32_t)(b < bblk_cap ? b : bblk_cap);
-}
-
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
-                 int32_t *smap, int64_t smap_cap, int32_t *bmap, int64_t bmap_cap,
-                 int32_t *partial, int64_t *tot, Counters *cnt, int64_t sblk_cap,
-                 int64_t bblk_cap, hipStream_t st) {
-  APIC_LAUNCH(k_copy_totals, dim3(1), dim3(1), 0, st, cnt, tot);
-  fill_i32(smap, 0, smap_cap, &tot[5], 1, st);
-  fill_i32(bmap, 0, bmap_cap, &tot[6], 1, st);
+                 int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
+                 int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
+                 int64_t sblk_cap, int64_t bblk_cap, hipStream_t st) {
   unsigned g = (unsigned)((seg_cap * 8 + 255) / 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  APIC_LAUNCH(k_mark, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
-  scan_exclusive(smap, smap, smap_cap, &tot[5], &tot[2], partial, 1, st);
-  scan_exclusive(bmap, bmap, bmap_cap, &tot[6], &tot[3], partial, 1, st);
-  APIC_LAUNCH(k_seg_slots, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smap, smap_cap, bmap, bmap_cap);
-  APIC_LAUNCH(k_block_counts, dim3(1), dim3(1), 0, st, cnt, tot, sblk_cap, bblk_cap, smap_cap, bmap_cap);
+  APIC_LAUNCH(k_mark, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smark, smap_cap,
+              bmark, bmap_cap, tot);
+  scan_exclusive(smark, smap, smap_cap, &tot[5], &tot[2], lb, 1, st);
+  scan_exclusive(bmark, bmap, bmap_cap, &tot[6], &tot[3], lb, 1, st);
+  APIC_LAUNCH(k_seg_slots, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smark, smap,
+              smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap);
 }
 
 // Block-wide reduction of 256 records: one set of atomics per block when all
