@@ -260,6 +260,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kGMass, T * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kGBuf0, T * 3 * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kGBuf1, T * 3 * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kGBuf2, T * 3 * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kInvM, sizeof(double) * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kBMass, sizeof(double) * kNodesPerBlock * P.bblk_cap));
   TRY(W.ensure(kRecGather, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
   TRY(W.ensure(kRecItems, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
@@ -290,6 +292,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.g.mass = W.ptr[kGMass];
   P.g.buf[0] = W.ptr[kGBuf0];
   P.g.buf[1] = W.ptr[kGBuf1];
+  P.g.buf[2] = W.ptr[kGBuf2];
+  P.g.invm = (double *)W.ptr[kInvM];
   P.g.bmass = (double *)W.ptr[kBMass];
   // state that kernels keep between launches starts from zero (mark arrays)
   // or a fresh look-back epoch whenever its buffer is new
@@ -354,10 +358,6 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
                   P.item_cap, P.segtmp, P.item_off, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
               P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
-  fill_zero_f(P.g.mass, P.sblk_cap, &P.cnt->n_sblocks, kNodesPerBlock, sizeof(T), st);
-  fill_zero_f(P.g.buf[0], P.sblk_cap, &P.cnt->n_sblocks, 3 * kNodesPerBlock, sizeof(T), st);
-  fill_zero_f(P.g.bmass, P.bblk_cap, &P.cnt->n_bblocks, kNodesPerBlock, sizeof(double), st);
-  if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   StepArgs a;
   a.sc = P.sc;
   a.seg = P.seg;
@@ -370,27 +370,21 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.xcd_split = P.xcd_split;
   a.item_wg = P.item_wg;
   a.group = P.group;
+  launch_grid_clear<T>(a, P.g, st);
+  if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
   launch_mass<T>(a, t, m_sorted, P.g, st);
   if (P.max_iter > 0) launch_normals<T>(a, t, nrm, P.g, st);
   if (prof) prof->end(APIC_KC_MASS, st), prof->begin(st);
   launch_p2g0<T>(a, t, m_sorted, vbar, P.g, st);
-  if (prof) prof->end(APIC_KC_P2G0, st), prof->begin(st);
-  launch_gridvel<T>(a, P.g, 0, st);
-  if (prof) prof->end(APIC_KC_GRIDVEL, st);
+  if (prof) prof->end(APIC_KC_P2G0, st);
   const uint32_t *perm_out = unpermute ? P.perm : nullptr;
-  int cur = 0;
   for (int k = 1; k <= P.max_iter + 1; ++k) {
     const bool final = k == P.max_iter + 1;
     if (prof) prof->begin(st);
-    launch_iter<T>(a, k, final, t, m_sorted, vbar, nrm, Y, P.g, cur, perm_out, v_out, C_out, st);
+    launch_iter<T>(a, k, final, t, m_sorted, vbar, nrm, Y, P.g, perm_out, v_out, C_out, st);
     if (prof) prof->end(final ? APIC_KC_FINAL : (k == 1 ? APIC_KC_ROUND1 : APIC_KC_ROUND), st);
-    if (final) break;
-    if (prof) prof->begin(st);
-    launch_gridvel<T>(a, P.g, 1 - cur, st);
-    if (prof) prof->end(APIC_KC_GRIDVEL, st);
-    cur = 1 - cur;
   }
   // momentum after (FP64) and, for the resident driver, the drift
   if (prof) prof->begin(st);
@@ -750,11 +744,11 @@ int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec
   const int64_t tb = prec == APIC_FP64 ? 8 : 4;
   if (blocks_hint <= 0) blocks_hint = n / 16 + 64;
   // resident state x2 (x, vC, m, body, orig), sorted scratch (t, m, normals,
-  // series), keys/values x2, segment/item tables; grid mass, 2 momentum
-  // buffers and per-body mass per node block.
+  // series), keys/values x2, segment/item tables; grid mass, 3 momentum
+  // buffers, 1/m and per-body mass per node block.
   int64_t per_particle = 2 * (tb * 16 + 2 + 4) + tb * (3 + 1 + 3 + 12) + 4 * 5 + 16 +
                          (int64_t)sizeof(Segment) + 2 * (int64_t)sizeof(Item);
-  int64_t per_block = kNodesPerBlock * (tb * 7 + 8) + 8 * 2;
+  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2;
   return n * per_particle + blocks_hint * per_block + (1 << 20);
 }
 

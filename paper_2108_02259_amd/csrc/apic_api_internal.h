@@ -31,7 +31,7 @@ namespace apic {
 enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
   kValsB, kGhist, kLbFlags, kLbState, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
-  kItemOff, kFlags, kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kBMass,
+  kItemOff, kFlags, kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kGBuf2, kInvM, kBMass,
   kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
 };
 

@@ -96,8 +96,9 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
 // ---- transfers (transfer.hip) ---------------------------------------------
 struct GridPtrs {
   void *mass;        // [sblk][64] T
-  void *buf[2];      // [sblk][3][64] T each
+  void *buf[3];      // [sblk][3][64] T each: grid momenta, rotating over the rounds
   double *bmass;     // [bblk][64]
+  double *invm;      // [sblk][64]: 1 / mass (0 where the mass is 0)
 };
 
 struct StepArgs {
@@ -121,16 +122,20 @@ void launch_normals(const StepArgs &a, const T *t, T *nrm, GridPtrs g, hipStream
 template <typename T>
 void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
                  hipStream_t st);
+// Zero the grid mass, the first two momentum buffers and the body masses of
+// the active blocks (counts on the device).
 template <typename T>
-void launch_gridvel(const StepArgs &a, GridPtrs g, int cur, hipStream_t st);
-// One fused round k >= 1: G2P of buffer `cur`, the rule, P2G of the next
-// series field into buffer 1-cur.  Scenes whose n_iter == k-1 finish here
-// (writing Vhat to v_out/C_out at perm[i], or at i when perm is null).
-// `final` selects the finishing-only kernel (k = max n_iter + 1).
+void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st);
+// One fused round k >= 1: G2P of the momenta in buffer (k-1) mod 3 (turned
+// into velocities q/m as the tile is loaded), the rule, P2G of the next series
+// field into buffer k mod 3, and clearing of buffer (k+1) mod 3 for round
+// k+1.  Scenes whose n_iter == k-1 finish here (writing Vhat to v_out/C_out at
+// perm[i], or at i when perm is null).  `final` selects the finishing-only
+// kernel (k = max n_iter + 1).
 template <typename T>
 void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
-                 const T *nrm, T *Y, GridPtrs g, int cur, const uint32_t *perm, T *v_out,
-                 T *C_out, hipStream_t st);
+                 const T *nrm, T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out,
+                 hipStream_t st);
 // FP64 momentum after the step (+ the resident driver's drift).
 template <typename T>
 void launch_after(int64_t n, const uint32_t *perm, T *x, const T *v, const T *C,

@@ -290,6 +290,24 @@ __device__ __forceinline__ void load_tile(T (*tile)[kTileSize], const T *buf, co
   }
 }
 
+// The 8x8x8 node velocities of a tile from grid momenta: v = q / m, formed as
+// q * (1/m) in FP64 (0 where the mass is 0), then stored in T.
+template <typename T>
+__device__ __forceinline__ void load_vel_tile(T (*tile)[kTileSize], const T *q, const double *invm,
+                                              const int32_t *slot) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int s = slot[j];
+    const int li = tile_index_block(j, lane);
+    const double inv = s >= 0 ? invm[(int64_t)s * kNodesPerBlock + lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      tile[c][li] =
+          s >= 0 ? (T)((double)q[((int64_t)s * 3 + c) * kNodesPerBlock + lane] * inv) : T(0);
+  }
+}
+
 template <typename T, int NC>
 __device__ __forceinline__ void flush_tile(T (*tile)[kTileSize], T *buf, const int32_t *slot,
                                            int comps_in_buf) {
@@ -599,28 +617,34 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
     }
     flush_group<T, G, 3>(a, tq, gl, member, it.seg, (T *)g.buf[0], 3);
   }
+  // side job for the rounds (the mass grid is complete since the mass kernel):
+  // 1 / m per active node in FP64, 0 where m = 0
+  const T *mass = (const T *)g.mass;
+  const int64_t nodes = (int64_t)a.cnt->n_sblocks * kNodesPerBlock;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nodes;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const double mi = (double)mass[q];
+    g.invm[q] = mi > 0.0 ? 1.0 / mi : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// grid velocity v_i = (m_i v_i) / m_i in FP64 (0 where m_i = 0), in place;
-// the other buffer is cleared for the next scatter.
+// step-start clear of the accumulation targets
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gridvel(const Counters *cnt, const T *mass, T *cur,
-                                                 T *other) {
-  const int64_t total = (int64_t)cnt->n_sblocks * kNodesPerBlock;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t slot = q >> 6, node = q & 63;
-    const double mi = (double)mass[q];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t idx = (slot * 3 + c) * kNodesPerBlock + node;
-      const double p = (double)cur[idx];
-      cur[idx] = mi > 0.0 ? (T)(p / mi) : T(0);
-      other[idx] = T(0);
-    }
+__global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass, T *q0, T *q1,
+                                                    double *bmass) {
+  const int64_t sn = (int64_t)cnt->n_sblocks * kNodesPerBlock;
+  const int64_t bn = (int64_t)cnt->n_bblocks * kNodesPerBlock;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * sn; q += stride) {
+    q0[q] = T(0);
+    q1[q] = T(0);
+    if (q < sn) mass[q] = T(0);
+    if (q < bn) bmass[q] = 0.0;
   }
+  for (int64_t q = 3 * sn + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn; q += stride)
+    bmass[q] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -634,15 +658,22 @@ __global__ __launch_bounds__(256) void k_gridvel(const Counters *cnt, const T *m
 template <typename T, bool FIRST, bool FINAL, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
 void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *nrm, T *Y,
-            GridPtrs g, int cur, const uint32_t *perm, T *v_out, T *C_out) {
+            GridPtrs g, const uint32_t *perm, T *v_out, T *C_out) {
   // One tile per wave: the gathered grid velocities, then (cleared) the
   // scatter target.
   __shared__ T tile[G][3][kTileSize];
   __shared__ GroupLds<G> gl;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n = a.n;
-  const T *gcur = (const T *)g.buf[cur];
-  T *gnext = (T *)g.buf[1 - cur];
+  const T *gcur = (const T *)g.buf[(k - 1) % 3];
+  T *gnext = (T *)g.buf[k % 3];
+  if (!FINAL) {  // the buffer round k+1 scatters into (last read by round k-1)
+    T *gclear = (T *)g.buf[(k + 1) % 3];
+    const int64_t words = (int64_t)a.cnt->n_sblocks * 3 * kNodesPerBlock;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < words;
+         q += (int64_t)gridDim.x * blockDim.x)
+      gclear[q] = T(0);
+  }
   for (ItemLoop L = item_loop(a, G); L.w < L.end; L.w += L.step) {
     const int w0 = L.w * G;
     if (a.items[w0].count == 0) continue;  // padding only (uniform over the workgroup)
@@ -653,7 +684,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
     const SceneDev &sd = a.sc[sg.scene];
     if (sd.n_iter < k - 1) continue;  // scene already finished (uniform per group)
     const bool finishing = FINAL || sd.n_iter == k - 1;
-    if (member) load_tile<T, 3>(tile[wave], gcur, sg.sslot, 3);
+    if (member) load_vel_tile<T>(tile[wave], gcur, g.invm, sg.sslot);
     wave_sync();
     const bool active = member && lane < it.count;
     const int64_t i = it.start + (active ? lane : 0);
@@ -768,28 +799,28 @@ void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridP
 }
 
 template <typename T>
-void launch_gridvel(const StepArgs &a, GridPtrs g, int cur, hipStream_t st) {
-  APIC_LAUNCH((k_gridvel<T>), dim3(a.node_wg), dim3(256), 0, st, a.cnt, (const T *)g.mass,
-              (T *)g.buf[cur], (T *)g.buf[1 - cur]);
+void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st) {
+  APIC_LAUNCH((k_grid_clear<T>), dim3(a.node_wg), dim3(256), 0, st, a.cnt, (T *)g.mass,
+              (T *)g.buf[0], (T *)g.buf[1], g.bmass);
 }
 
 template <typename T>
 void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
-                 const T *nrm, T *Y, GridPtrs g, int cur, const uint32_t *perm, T *v_out,
-                 T *C_out, hipStream_t st) {
+                 const T *nrm, T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out,
+                 hipStream_t st) {
   // finishing-only rounds scatter nothing: one wave per item
   if (final) {
     if (k == 1)
       APIC_LAUNCH((k_iter<T, true, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m, vbar,
-                  nrm, Y, g, cur, perm, v_out, C_out);
+                  nrm, Y, g, perm, v_out, C_out);
     else
       APIC_LAUNCH((k_iter<T, false, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m,
-                  vbar, nrm, Y, g, cur, perm, v_out, C_out);
+                  vbar, nrm, Y, g, perm, v_out, C_out);
     return;
   }
 #define L_ITER(FIRST_) \
   APIC_LAUNCH((k_iter<T, FIRST_, false, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
-              vbar, nrm, Y, g, cur, perm, v_out, C_out)
+              vbar, nrm, Y, g, perm, v_out, C_out)
   if (k == 1)
     APIC_GROUP_DISPATCH(L_ITER, true);
   else
@@ -802,9 +833,9 @@ void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, c
   template void launch_normals<T>(const StepArgs &, const T *, T *, GridPtrs, hipStream_t);     \
   template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, GridPtrs,     \
                                hipStream_t);                                                    \
-  template void launch_gridvel<T>(const StepArgs &, GridPtrs, int, hipStream_t);                \
+  template void launch_grid_clear<T>(const StepArgs &, GridPtrs, hipStream_t);                 \
   template void launch_iter<T>(const StepArgs &, int, bool, const T *, const T *, const T *,     \
-                               const T *, T *, GridPtrs, int, const uint32_t *, T *, T *,       \
+                               const T *, T *, GridPtrs, const uint32_t *, T *, T *,            \
                                hipStream_t);
 INST(float)
 INST(double)
