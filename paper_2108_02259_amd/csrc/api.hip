@@ -325,8 +325,9 @@ static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *
 // keys + sort; sets P.keys / P.perm.  The contact step needs particles
 // grouped by (scene, body, block) only -- the per-cell pass ranking works in
 // any order within a block -- so it sorts by the block part of the key
-// (bits 6 and up) and keeps input order within a block; full_key sorts by
-// the whole key (the ordering apic_sort_keys returns).
+// (bits 6 and up) and keeps input order within a block (the gather then
+// orders each wave's particles by cell, which costs no pass over memory);
+// full_key sorts by the whole key (the ordering apic_sort_keys returns).
 template <typename T>
 static void enqueue_sort(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
                          Profiler *prof, bool full_key = false) {
@@ -350,8 +351,15 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   const int64_t n = P.n;
   if (prof) prof->begin(st);
   fill_bytes_zero(P.red, sizeof(double) * kRed * 2 * P.ns, st);
-  launch_gather<T>(P.perm, n, x, v, C, m, body, P.sc, P.ns, (T *)P.t, vbar, m_sorted, P.sbody,
-                   x_sorted, body_sorted, orig_in, orig_out, P.rec_gather, P.red, st);
+  // the gather also orders each wave's particles by cell within a block, and
+  // writes that order's keys and permutation into the sort's free buffers
+  uint32_t *keys2 = P.keys == P.ka ? P.kb : P.ka;
+  uint32_t *perm2 = P.perm == P.va ? P.vb : P.va;
+  launch_gather<T>(P.perm, P.keys, n, x, v, C, m, body, P.sc, P.ns, (T *)P.t, vbar, m_sorted,
+                   P.sbody, x_sorted, body_sorted, orig_in, orig_out, keys2, perm2, P.rec_gather,
+                   P.red, st);
+  P.keys = keys2;
+  P.perm = perm2;
   launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
   launch_segments(P.keys, n, P.flags, P.lb, P.tot, P.sbody, P.blay, P.seg, P.seg_cap, P.items,

@@ -74,12 +74,17 @@ void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, cons
 template <typename T>
 void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
                  const BodyLay *blay, uint32_t *keys, hipStream_t st);
+// Gather the particle state into sorted order.  keys/perm come from the
+// block-order sort; within each wave the particles are further ordered by
+// cell (stable), and that final order's keys and permutation go to
+// keys_out/perm_out (distinct from keys/perm).
 template <typename T>
-void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
-                   const T *m, const uint16_t *body, const SceneDev *sc, int ns,
-                   T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
+void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const T *x,
+                   const T *v, const T *C, const T *m, const uint16_t *body, const SceneDev *sc,
+                   int ns, T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
                    T *x_out, uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
-                   RedRec *rec, double *direct, hipStream_t st);
+                   uint32_t *keys_out, uint32_t *perm_out, RedRec *rec, double *direct,
+                   hipStream_t st);
 void launch_segments(const uint32_t *keys, int64_t n, int32_t *seg_id, const Lookback &lb,
                      int64_t *tot, const int32_t *sbody, const BodyLay *blay,
                      Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,

@@ -434,20 +434,57 @@ __device__ __forceinline__ void momentum_terms(const double r[3], const double v
   q[10] = 0.0;
 }
 
+// Position of this lane's particle once the 64 sorted particles of its wave
+// are also ordered by cell within each block: the sort orders by block only,
+// so each block's particles form a run of lanes; a particle's new lane is its
+// run's first lane plus its stable rank by 6-bit cell key within the run.
+// (Lanes holding cells in x-fastest order keep the LDS tile accesses of the
+// transfer kernels free of bank conflicts.)
+__device__ __forceinline__ int64_t cell_order_slot(int64_t i, bool ok, uint32_t key) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t blk = key >> 6;
+  const uint32_t pblk = __shfl_up(blk, 1, 64);
+  const int pok = __shfl_up(ok ? 1 : 0, 1, 64);
+  const bool head = lane == 0 || pblk != blk || pok != (ok ? 1 : 0);
+  const uint64_t heads = __ballot(head);
+  const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
+  const int start = 63 - __clzll((unsigned long long)(heads & le));
+  const uint64_t later = heads & ~le;
+  const int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+  uint64_t eq = (end == 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << start) - 1);
+  const uint32_t cell = key & 63u;
+  int less = 0;
+#pragma unroll
+  for (int b = 5; b >= 0; --b) {
+    const bool bit = (cell >> b) & 1u;
+    const uint64_t m1 = __ballot(bit);
+    if (bit) less += __popcll(eq & ~m1);
+    eq &= bit ? m1 : ~m1;
+  }
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  return i - lane + start + less + __popcll(eq & lt);
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, int64_t n, const T *x,
+__global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, const uint32_t *keys,
+                                                int64_t n, const T *x,
                                                 const T *v, const T *C, const T *m,
                                                 const uint16_t *body, const SceneDev *sc, int ns,
                                                 T *t_out, T *vbar_out, T *m_out,
                                                 int32_t *sbody_out, T *x_out, uint16_t *body_out,
                                                 const uint32_t *orig_in, uint32_t *orig_out,
+                                                uint32_t *keys_out, uint32_t *perm_out,
                                                 RedRec *rec, double *direct) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = i < n;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i0 < n;
+  const uint32_t key = ok ? keys[i0] : 0u;
+  const int64_t i = cell_order_slot(i0, ok, key);
   int s = 0;
   double q[kRed];
   if (ok) {
-    const int64_t p = perm[i];
+    const int64_t p = perm[i0];
+    keys_out[i] = key;
+    perm_out[i] = (uint32_t)p;
     s = scene_of(sc, ns, p);
     const SceneDev sd = sc[s];
     CellInfo ci = cell_of(x, n, p, sd);
@@ -477,20 +514,20 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, int64_t n,
     if (orig_out) orig_out[i] = orig_in ? orig_in[p] : (uint32_t)p;
     if (rec) momentum_terms(r, vv, CC, (double)mv, sd.h, q);
   }
-  if (rec) reduce_scene(ok, s, q, rec, i >> 6, direct);
+  if (rec) reduce_scene(ok, s, q, rec, i0 >> 6, direct);
 }
 
 template <typename T>
-void launch_gather(const uint32_t *perm, int64_t n, const T *x, const T *v, const T *C,
-                   const T *m, const uint16_t *body, const SceneDev *sc, int ns, T *t_out,
-                   T *vbar_out, T *m_out, int32_t *sbody_out, T *x_out, uint16_t *body_out,
-                   const uint32_t *orig_in, uint32_t *orig_out, RedRec *rec, double *direct,
+void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const T *x, const T *v,
+                   const T *C, const T *m, const uint16_t *body, const SceneDev *sc, int ns,
+                   T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out, T *x_out,
+                   uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
+                   uint32_t *keys_out, uint32_t *perm_out, RedRec *rec, double *direct,
                    hipStream_t st) {
   if (n <= 0) return;
-  APIC_LAUNCH((k_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n, x, v, C, m, body, sc, ns,
-                                                            t_out, vbar_out, m_out, sbody_out,
-                                                            x_out, body_out, orig_in, orig_out,
-                                                            rec, direct);
+  APIC_LAUNCH((k_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, keys, n,
+              x, v, C, m, body, sc, ns, t_out, vbar_out, m_out, sbody_out, x_out, body_out,
+              orig_in, orig_out, keys_out, perm_out, rec, direct);
 }
 
 // Momentum after the contact step (and the drift x += dt v of the resident
@@ -812,15 +849,13 @@ template void launch_keys<float>(const float *, const uint16_t *, int64_t, const
                                  const BodyLay *, uint32_t *, hipStream_t);
 template void launch_keys<double>(const double *, const uint16_t *, int64_t, const SceneDev *, int,
                                   const BodyLay *, uint32_t *, hipStream_t);
-template void launch_gather<float>(const uint32_t *, int64_t, const float *, const float *,
-                                   const float *, const float *, const uint16_t *,
-                                   const SceneDev *, int, float *, float *, float *, int32_t *,
-                                   float *, uint16_t *, const uint32_t *, uint32_t *, RedRec *,
-                                   double *, hipStream_t);
-template void launch_gather<double>(const uint32_t *, int64_t, const double *, const double *,
-                                    const double *, const double *, const uint16_t *,
-                                    const SceneDev *, int, double *, double *, double *,
-                                    int32_t *, double *, uint16_t *, const uint32_t *, uint32_t *,
-                                    RedRec *, double *, hipStream_t);
+template void launch_gather<float>(const uint32_t *, const uint32_t *, int64_t, const float *,
+    const float *, const float *, const float *, const uint16_t *, const SceneDev *, int, float *,
+    float *, float *, int32_t *, float *, uint16_t *, const uint32_t *, uint32_t *, uint32_t *,
+    uint32_t *, RedRec *, double *, hipStream_t);
+template void launch_gather<double>(const uint32_t *, const uint32_t *, int64_t, const double *,
+    const double *, const double *, const double *, const uint16_t *, const SceneDev *, int, double *,
+    double *, double *, int32_t *, double *, uint16_t *, const uint32_t *, uint32_t *, uint32_t *,
+    uint32_t *, RedRec *, double *, hipStream_t);
 
 }  // namespace apic
