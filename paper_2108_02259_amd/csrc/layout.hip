@@ -461,8 +461,9 @@ __device__ __forceinline__ int64_t cell_order_slot(int64_t i, bool ok, uint32_t 
     if (bit) less += __popcll(eq & ~m1);
     eq &= bit ? m1 : ~m1;
   }
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  return i - lane + start + less + __popcll(eq & lt);
+  const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(eq >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)eq, 0u));
+  return i - lane + start + less + below;
 }
 
 template <typename T>

@@ -40,6 +40,71 @@ struct Stencil {
   __device__ __forceinline__ T wdx(int d, int a) const { return w[d][a] * dx(d, a); }
 };
 
+// Index of the calling wave in its workgroup, as a wave-uniform value (so
+// that what is derived from it -- work items, segments, slots -- lives in
+// scalar registers and is read with scalar loads).
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// Lane access to a wave-uniform array through a buffer resource: the base
+// address stays in scalar registers and each lane supplies only a 32-bit
+// byte offset, so no per-lane 64-bit address occupies vector registers (the
+// compiler otherwise keeps one such pair per array live across the item loop).
+// p must be wave-uniform; offsets are below 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lane_rsrc(const void *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ float lane_ld(const float *p, uint32_t li) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(lane_rsrc(p), li * 4u, 0, 0));
+}
+__device__ __forceinline__ double lane_ld(const double *p, uint32_t li) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(lane_rsrc(p), li * 8u, 0, 0));
+}
+__device__ __forceinline__ uint32_t lane_ld(const uint32_t *p, uint32_t li) {
+  return __builtin_amdgcn_raw_buffer_load_b32(lane_rsrc(p), li * 4u, 0, 0);
+}
+__device__ __forceinline__ void lane_st(float *p, uint32_t li, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), lane_rsrc(p), li * 4u, 0, 0);
+}
+__device__ __forceinline__ void lane_st(double *p, uint32_t li, double v) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(lane_rsrc(p), 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), lane_rsrc(p), li * 8u, 0, 0);
+}
+
+// The 12 values of one particle's row in a [n][12] array (row pointer p
+// wave-uniform, lane li reads row li), in 16-byte loads / stores.
+template <typename T>
+__device__ __forceinline__ void lane_ld12(const T *p, uint32_t li, T v[12]) {
+  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T);
+  const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
+#pragma unroll
+  for (int k = 0; k < 12 / kPer; ++k) {
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow + 16 * k, 0, 0);
+    T e[kPer];
+    __builtin_memcpy(e, &q, 16);
+#pragma unroll
+    for (int x = 0; x < kPer; ++x) v[k * kPer + x] = e[x];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void lane_st12(T *p, uint32_t li, const T v[12]) {
+  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T);
+  const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
+#pragma unroll
+  for (int k = 0; k < 12 / kPer; ++k) {
+    T e[kPer];
+#pragma unroll
+    for (int x = 0; x < kPer; ++x) e[x] = v[k * kPer + x];
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
+    __builtin_memcpy(&q, e, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow + 16 * k, 0, 0);
+  }
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Per-axis basis of Appendix B at cell-relative coordinate t in [0, 1):
 // nodes c-1..c+2 carry (1-t)^2/4, (2-t^2)/4, (1+2t-t^2)/4, t^2/4.
 template <typename T>
@@ -157,7 +222,8 @@ __device__ __forceinline__ void p2g(T (*tq)[kTileSize], int base, const Stencil<
       for (int c = 0; c < 4; ++c) {
         const int idx = base + a + kTileX * b + kTileZStride * c;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) tq[q][idx] += S.w[2][c] * P[q] + S.wdx(2, c) * Q[q];
+        for (int q = 0; q < 3; ++q)
+          tq[q][idx] = fma_t(S.w[2][c], P[q], fma_t(S.wdx(2, c), Q[q], tq[q][idx]));
         LDS_ORDER();
       }
     }
@@ -196,9 +262,10 @@ __device__ __forceinline__ int cell_rank(bool active, uint32_t cell6, int *passe
     const uint64_t bb = __ballot((cell6 >> b) & 1u);
     peers &= ((cell6 >> b) & 1u) ? bb : ~bb;
   }
-  const int lane = threadIdx.x & 63;
-  const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  int rank = active ? __popcll(peers & lower) : 0;
+  // set bits of peers below this lane (mbcnt: no lane mask kept in registers)
+  const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+  int rank = active ? below : 0;
   int mx = active ? rank : 0;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
@@ -291,20 +358,31 @@ __device__ __forceinline__ void load_tile(T (*tile)[kTileSize], const T *buf, co
 }
 
 // The 8x8x8 node velocities of a tile from grid momenta: v = q / m, formed as
-// q * (1/m) in FP64 (0 where the mass is 0), then stored in T.
+// q * (1/m) in FP64 (0 where the mass is 0), then stored in T.  All eight
+// slots are read first and then every block's loads are issued together
+// (absent blocks read block 0 and are masked), so the tile costs two memory
+// round trips rather than two per block.
 template <typename T>
 __device__ __forceinline__ void load_vel_tile(T (*tile)[kTileSize], const T *q, const double *invm,
                                               const int32_t *slot) {
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63;
+  int s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = __builtin_amdgcn_readfirstlane(slot[j]);
+  T v[8][3];
+  double inv[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int s = slot[j];
-    const int li = tile_index_block(j, lane);
-    const double inv = s >= 0 ? invm[(int64_t)s * kNodesPerBlock + lane] : 0.0;
+    const int64_t sj = s[j] >= 0 ? s[j] : 0;
+    inv[j] = lane_ld(invm + sj * kNodesPerBlock, lane);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      tile[c][li] =
-          s >= 0 ? (T)((double)q[((int64_t)s * 3 + c) * kNodesPerBlock + lane] * inv) : T(0);
+    for (int c = 0; c < 3; ++c) v[j][c] = lane_ld(q + (sj * 3 + c) * kNodesPerBlock, lane);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int li = tile_index_block(j, lane);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tile[c][li] = s[j] >= 0 ? (T)((double)v[j][c] * inv[j]) : T(0);
   }
 }
 
@@ -443,13 +521,16 @@ __device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl)
 }
 
 // Sum the covering waves' tiles per node (wave order) and add each nonzero
-// sum once to the global buffer; the tiles read are left zero.
+// sum once to the global buffer; the tiles read are left zero.  Wave v of
+// the workgroup takes node blocks J = v, v + G, ..., one node per lane, so
+// everything about J is wave-uniform.
 template <typename T, int G, int NC>
 __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const GroupLds<G> &gl,
                                             T *buf, int comps_in_buf) {
-  for (int idx = threadIdx.x; idx < 27 * kNodesPerBlock; idx += 64 * G) {
-    const int J = idx >> 6, node = idx & 63;
-    const uint32_t mask = gl.mask[J];
+  const int lane = threadIdx.x & 63;
+  const int loff = tile_index_block(0, lane);
+  for (int J = wave_id(); J < 27; J += G) {
+    const uint32_t mask = __builtin_amdgcn_readfirstlane(gl.mask[J]);
     if (!mask) continue;
     const int Jx = J % 3, Jy = (J / 3) % 3, Jz = J / 9;
     T sum[NC];
@@ -458,20 +539,21 @@ __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const Gro
 #pragma unroll
     for (int w = 0; w < G; ++w) {
       if (!((mask >> w) & 1u)) continue;
-      const int sb = gl.sbi[w];
+      const int sb = __builtin_amdgcn_readfirstlane(gl.sbi[w]);
       const int j = (Jx - (sb & 1)) + 2 * (Jy - ((sb >> 1) & 1)) + 4 * (Jz - (sb >> 2));
-      const int li = tile_index_block(j, node);
+      const int li = tile_index_block(j, 0) + loff;
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         sum[q] += tiles[w][q][li];
         tiles[w][q][li] = T(0);
       }
     }
-    const int s = gl.slot[J];
+    const int s = __builtin_amdgcn_readfirstlane(gl.slot[J]);
+    if (s < 0) continue;
+    T *dst = buf + (int64_t)s * comps_in_buf * kNodesPerBlock;
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-      if (sum[q] != T(0) && s >= 0)
-        unsafeAtomicAdd(&buf[((int64_t)s * comps_in_buf + q) * kNodesPerBlock + node], sum[q]);
+      if (sum[q] != T(0)) unsafeAtomicAdd(&dst[q * kNodesPerBlock + lane], sum[q]);
   }
 }
 
@@ -486,10 +568,12 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
     if (flushes) flush_tile<T, NC>(tiles[0], buf, a.seg[seg_index].sslot, comps_in_buf);
     wave_sync();
   } else {
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
+    const int sgi = flushes ? seg_index : -1;  // wave-uniform
+    const int sbi = flushes ? block_in_super(a.seg[seg_index]) : 0;
     if ((threadIdx.x & 63) == 0) {
-      gl.seg[wave] = flushes ? seg_index : -1;
-      gl.sbi[wave] = flushes ? block_in_super(a.seg[seg_index]) : 0;
+      gl.seg[wave] = sgi;
+      gl.sbi[wave] = sbi;
     }
     __syncthreads();
     group_tables<G>(a, gl);
@@ -508,7 +592,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
   __shared__ T tm[G][1][kTileSize];
   __shared__ T tb[G][1][kTileSize];  // one item's body mass; flushed into FP64
   __shared__ GroupLds<G> gl;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   zero_tile<T, 1>(tm[wave]);
   zero_tile<T, 1>(tb[wave]);
   wave_sync();
@@ -582,7 +666,7 @@ __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G
 void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
   __shared__ T tq[G][3][kTileSize];
   __shared__ GroupLds<G> gl;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   zero_tile<T, 3>(tq[wave]);
   wave_sync();
   const int64_t n = a.n;
@@ -653,6 +737,7 @@ __global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass
 // Stored per particle between rounds: Y = D_{k-1} - W_k, so that after the
 // next G2P (of W_k) the accumulated change is D_k = Y + H W_k, and the final
 // answer is Vhat = Vbar + D_N.  Round 1 starts from D_0 = H Vbar - Vbar.
+// Y is laid out by particle ([n][12], sorted order): one row per lane.
 // Scenes with n_iter == k-1 finish in round k: they write Vhat and scatter
 // nothing.  FINAL rounds only finish.
 template <typename T, bool FIRST, bool FINAL, int G>
@@ -663,7 +748,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
   // scatter target.
   __shared__ T tile[G][3][kTileSize];
   __shared__ GroupLds<G> gl;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int64_t n = a.n;
   const T *gcur = (const T *)g.buf[(k - 1) % 3];
   T *gnext = (T *)g.buf[k % 3];
@@ -687,46 +772,57 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
     if (member) load_vel_tile<T>(tile[wave], gcur, g.invm, sg.sslot);
     wave_sync();
     const bool active = member && lane < it.count;
-    const int64_t i = it.start + (active ? lane : 0);
-    const uint32_t key = a.keys[i];
+    // per-particle arrays: wave-uniform base it.start (+ c n), lane offset li
+    const uint32_t li = active ? lane : 0u;
+    const int64_t i0 = it.start;
+    const uint32_t key = lane_ld(a.keys + i0, li);
     const int base = particle_base(key);
     const T h = (T)sd.h;
     Stencil<T> S;
     T W[12];
     if (active) {
       T tt[3];
-      load_t(t, n, i, tt);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
       make_stencil(tt, h, S);
       T hv[3], hC[9];
       g2p(tile[wave], base, S, T(2) / (h * h), hv, hC);
+      const T *vbi = vbar + i0;
+      const T *Yi = Y + 12 * i0;  // Y rows: [n][12]
       if (finishing) {
-        const int64_t dst = perm ? (int64_t)perm[i] : i;
+        const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
 #pragma unroll
           for (int c = 0; c < 3; ++c) v_out[c * n + dst] = hv[c];
 #pragma unroll
           for (int c = 0; c < 9; ++c) C_out[c * n + dst] = hC[c];
         } else {
+          T yr[12];
+          lane_ld12(Yi, li, yr);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) v_out[c * n + dst] = vbar[c * n + i] + (Y[c * n + i] + hv[c]);
+          for (int c = 0; c < 3; ++c) v_out[c * n + dst] = lane_ld(vbi + c * n, li) + (yr[c] + hv[c]);
 #pragma unroll
           for (int c = 0; c < 9; ++c)
-            C_out[c * n + dst] = vbar[(3 + c) * n + i] + (Y[(3 + c) * n + i] + hC[c]);
+            C_out[c * n + dst] = lane_ld(vbi + (3 + c) * n, li) + (yr[3 + c] + hC[c]);
         }
       } else if (!FINAL) {
         T D[12];
         if (FIRST) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) D[c] = hv[c] - vbar[c * n + i];
+          for (int c = 0; c < 3; ++c) D[c] = hv[c] - lane_ld(vbi + c * n, li);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - vbar[(3 + c) * n + i];
+          for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - lane_ld(vbi + (3 + c) * n, li);
         } else {
+          T yr[12];
+          lane_ld12(Yi, li, yr);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) D[c] = Y[c * n + i] + hv[c];
+          for (int c = 0; c < 3; ++c) D[c] = yr[c] + hv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) D[3 + c] = Y[(3 + c) * n + i] + hC[c];
+          for (int c = 0; c < 9; ++c) D[3 + c] = yr[3 + c] + hC[c];
         }
-        const double nd[3] = {(double)nrm[i], (double)nrm[n + i], (double)nrm[2 * n + i]};
+        const T *ni = nrm + i0;
+        const double nd[3] = {(double)lane_ld(ni, li), (double)lane_ld(ni + n, li),
+                              (double)lane_ld(ni + 2 * n, li)};
         if (nd[0] == 0.0 && nd[1] == 0.0 && nd[2] == 0.0) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) W[c] = T(0);
@@ -739,8 +835,10 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
 #pragma unroll
           for (int c = 0; c < 9; ++c) W[3 + c] = D[3 + c];
         }
+        T yr[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) Y[c * n + i] = D[c] - W[c];
+        for (int c = 0; c < 12; ++c) yr[c] = D[c] - W[c];
+        lane_st12(Y + 12 * i0, li, yr);
       }
     }
     if (!FINAL && !finishing) {
@@ -751,7 +849,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       if (member) zero_tile<T, 3>(tile[wave]);
       wave_sync();
       if (active) {
-        const T mp = m[i];
+        const T mp = lane_ld(m + i0, li);
         for (int pass = 0; pass < passes; ++pass) {
           if (rank == pass) p2g(tile[wave], base, S, mp, W, W + 3);
           LDS_ORDER();
