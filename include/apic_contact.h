@@ -193,8 +193,8 @@ enum {
   APIC_KC_SORT = 1,     /* radix sort passes */
   APIC_KC_GATHER = 2,   /* permute state into sorted order, momentum before */
   APIC_KC_SEGMENTS = 3, /* segments, work items, node-block maps, grid clear */
-  APIC_KC_MASS = 4,     /* grid mass, per-body mass and contact normals */
-  APIC_KC_P2G0 = 5,     /* Vbar to grid */
+  APIC_KC_MASS = 4,     /* grid mass and per-body mass */
+  APIC_KC_P2G0 = 5,     /* contact normals and Vbar to grid */
   APIC_KC_GRIDVEL = 6,  /* (no kernels: grid velocities are formed as the rounds
                            load their tiles) */
   APIC_KC_ROUND1 = 7,   /* first series round (G2P + rule + P2G) */

@@ -383,9 +383,8 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
   launch_mass<T>(a, t, m_sorted, P.g, st);
-  if (P.max_iter > 0) launch_normals<T>(a, t, nrm, P.g, st);
   if (prof) prof->end(APIC_KC_MASS, st), prof->begin(st);
-  launch_p2g0<T>(a, t, m_sorted, vbar, P.g, st);
+  launch_p2g0<T>(a, t, m_sorted, vbar, nrm, P.g, st);
   if (prof) prof->end(APIC_KC_P2G0, st);
   const uint32_t *perm_out = unpermute ? P.perm : nullptr;
   for (int k = 1; k <= P.max_iter + 1; ++k) {

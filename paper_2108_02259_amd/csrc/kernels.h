@@ -122,10 +122,10 @@ struct StepArgs {
 
 template <typename T>
 void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStream_t st);
+// Contact normals (where a scene has series rounds) and P2G of Vbar into
+// buffer 0, in one pass over the items (after launch_mass).
 template <typename T>
-void launch_normals(const StepArgs &a, const T *t, T *nrm, GridPtrs g, hipStream_t st);
-template <typename T>
-void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
+void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g,
                  hipStream_t st);
 // Zero the grid mass, the first two momentum buffers and the body masses of
 // the active blocks (counts on the device).

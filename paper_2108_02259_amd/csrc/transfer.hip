@@ -13,10 +13,10 @@
 // The quadratic spline weights are separable, so P2G and G2P use per-axis
 // partial sums (about 580 FMA each per particle instead of 1000+).
 //
-// One step runs: k_mass (grid mass and per-body mass), k_normals (contact
-// normals), k_p2g0 (Vbar to grid), then for k = 1..N the fused round k_iter
-// (G2P of the previous field, the rule, P2G of the next series field), and
-// the final G2P.  The grid velocity q/m is formed in between by k_gridvel.
+// One step runs: k_mass (grid mass and per-body mass), k_p2g0 (contact
+// normals and Vbar to grid), then for k = 1..N the fused round k_iter (G2P
+// of the previous field, the rule, P2G of the next series field), and the
+// final G2P.  Grid velocities q/m are formed as the rounds load their tiles.
 //
 // Precision: T = float for the mixed path (weights, P2G/G2P accumulation,
 // grid momenta), T = double for the plain FP64 path.  Grid velocity q/m,
@@ -230,10 +230,10 @@ __device__ __forceinline__ void p2g(T (*tq)[kTileSize], int base, const Stencil<
   }
 }
 
-// Mass P2G (eq. massToGrid): N m to the shared mass tile (T) and the body's
-// mass tile (double), with the same race-freedom argument as p2g.
+// Mass P2G (eq. massToGrid): N m to the mass tile, with the same
+// race-freedom argument as p2g.
 template <typename T>
-__device__ __forceinline__ void p2g_mass(T *tm, T *tb, int base, const Stencil<T> &S, T m) {
+__device__ __forceinline__ void p2g_mass(T *tm, int base, const Stencil<T> &S, T m) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -243,9 +243,7 @@ __device__ __forceinline__ void p2g_mass(T *tm, T *tb, int base, const Stencil<T
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int idx = base + a + kTileX * b + kTileZStride * c;
-        const T wm = wab * S.w[2][c];
-        tm[idx] += wm;
-        tb[idx] += wm;
+        tm[idx] += wab * S.w[2][c];
         LDS_ORDER();
       }
     }
@@ -343,17 +341,29 @@ __device__ __forceinline__ void undesirable(const double d[3], const double n[3]
   for (int a = 0; a < 3; ++a) w[a] = tau > 0.0 ? dt[a] - s * dt[a] / tau : 0.0;
 }
 
+// Tile of NC components from a [slot][comps_in_buf][64] buffer: slots
+// first, then every block's loads together (absent blocks read block 0 and
+// are masked).
 template <typename T, int NC>
 __device__ __forceinline__ void load_tile(T (*tile)[kTileSize], const T *buf, const int32_t *slot,
                                           int comps_in_buf) {
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63;
+  int s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = __builtin_amdgcn_readfirstlane(slot[j]);
+  T v[8][NC];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int s = slot[j];
-    const int li = tile_index_block(j, lane);
+    const int64_t sj = s[j] >= 0 ? s[j] : 0;
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-      tile[q][li] = s >= 0 ? buf[((int64_t)s * comps_in_buf + q) * kNodesPerBlock + lane] : T(0);
+      v[j][q] = lane_ld(buf + (sj * comps_in_buf + q) * kNodesPerBlock, lane);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int li = tile_index_block(j, lane);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) tile[q][li] = s[j] >= 0 ? v[j][q] : T(0);
   }
 }
 
@@ -404,20 +414,6 @@ __device__ __forceinline__ void flush_tile(T (*tile)[kTileSize], T *buf, const i
   }
 }
 
-// One-component flush into a buffer of a wider type (body mass: T -> double).
-template <typename T, typename U>
-__device__ __forceinline__ void flush_tile_to(T (*tile)[kTileSize], U *buf, const int32_t *slot) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int s = slot[j];
-    const int li = tile_index_block(j, lane);
-    const T v = tile[0][li];
-    tile[0][li] = T(0);
-    if (v != T(0) && s >= 0) unsafeAtomicAdd(&buf[(int64_t)s * kNodesPerBlock + lane], (U)v);
-  }
-}
-
 template <typename T, int NC>
 __device__ __forceinline__ void zero_tile(T (*tile)[kTileSize]) {
   const int lane = threadIdx.x & 63;
@@ -431,13 +427,6 @@ __device__ __forceinline__ void zero_tile(T (*tile)[kTileSize]) {
 // within a wavefront, so a compiler ordering point replaces the workgroup
 // barrier -- and, unlike a barrier, does not wait for the flush atomics.
 __device__ __forceinline__ void wave_sync() { LDS_ORDER(); }
-
-template <typename T>
-__device__ __forceinline__ void load_t(const T *t, int64_t n, int64_t i, T tt[3]) {
-  tt[0] = t[i];
-  tt[1] = t[n + i];
-  tt[2] = t[2 * n + i];
-}
 
 __device__ __forceinline__ int item_count(const StepArgs &a) {
   return a.cnt->err ? 0 : a.cnt->n_items;
@@ -488,6 +477,7 @@ __device__ __forceinline__ ItemLoop item_loop(const StepArgs &a, int unit = 1) {
 template <int G>
 struct GroupLds {
   int32_t slot[27];   // shared-grid slot of super node block J (-1: none)
+  int32_t bslot[27];  // body-grid slot of J (mass kernel; the group is one body)
   uint32_t mask[27];  // waves whose tile covers J
   int32_t sbi[G];     // wave's block within the super block, x + 2y + 4z
   int32_t seg[G];     // wave's segment, -1 if it has nothing to flush
@@ -499,13 +489,13 @@ __device__ __forceinline__ int block_in_super(const Segment &sg) {
 
 // Cover masks and slots of the 27 node blocks (after every wave has filled
 // its sbi/seg entry and a barrier).
-template <int G>
+template <int G, bool BODY = false>
 __device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl) {
   const int t = threadIdx.x;
   if (t < 27) {
     const int Jx = t % 3, Jy = (t / 3) % 3, Jz = t / 9;
     uint32_t mask = 0;
-    int32_t slot = -1;
+    int32_t slot = -1, bslot = -1;
     for (int w = 0; w < G; ++w) {
       const int sgi = gl.seg[w];
       if (sgi < 0) continue;
@@ -514,9 +504,11 @@ __device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl)
       if (jx < 0 || jx > 1 || jy < 0 || jy > 1 || jz < 0 || jz > 1) continue;
       mask |= 1u << w;
       slot = a.seg[sgi].sslot[jx + 2 * jy + 4 * jz];
+      if (BODY) bslot = a.seg[sgi].bslot[jx + 2 * jy + 4 * jz];
     }
     gl.mask[t] = mask;
     gl.slot[t] = slot;
+    if (BODY) gl.bslot[t] = bslot;
   }
 }
 
@@ -583,18 +575,82 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
   }
 }
 
+// Flush of a group's mass tiles into both the shared grid mass (T, by
+// sslot) and the body grid mass (FP64, by bslot).  An item's contribution to
+// its body's grid equals its contribution to the shared grid, and a group is
+// one body, so one tile per wave serves both; the body sums are formed in
+// FP64.  The tiles read are left zero.
+template <typename T, int G>
+__device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1][kTileSize],
+                                                 GroupLds<G> &gl, bool flushes, int seg_index,
+                                                 T *mass, double *bmass) {
+  const int lane = threadIdx.x & 63;
+  if (G == 1) {
+    wave_sync();
+    if (flushes) {
+      const Segment &sg = a.seg[seg_index];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int s = __builtin_amdgcn_readfirstlane(sg.sslot[j]);
+        const int b = __builtin_amdgcn_readfirstlane(sg.bslot[j]);
+        const int li = tile_index_block(j, lane);
+        const T v = tiles[0][0][li];
+        tiles[0][0][li] = T(0);
+        if (v != T(0)) {
+          if (s >= 0) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], v);
+          if (b >= 0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], (double)v);
+        }
+      }
+    }
+    wave_sync();
+    return;
+  }
+  const int wave = wave_id();
+  const int sgi = flushes ? seg_index : -1;
+  const int sbi = flushes ? block_in_super(a.seg[seg_index]) : 0;
+  if (lane == 0) {
+    gl.seg[wave] = sgi;
+    gl.sbi[wave] = sbi;
+  }
+  __syncthreads();
+  group_tables<G, true>(a, gl);
+  __syncthreads();
+  const int loff = tile_index_block(0, lane);
+  for (int J = wave; J < 27; J += G) {
+    const uint32_t mask = __builtin_amdgcn_readfirstlane(gl.mask[J]);
+    if (!mask) continue;
+    const int Jx = J % 3, Jy = (J / 3) % 3, Jz = J / 9;
+    T sum = T(0);
+    double sumd = 0.0;
+#pragma unroll
+    for (int w = 0; w < G; ++w) {
+      if (!((mask >> w) & 1u)) continue;
+      const int sb = __builtin_amdgcn_readfirstlane(gl.sbi[w]);
+      const int j = (Jx - (sb & 1)) + 2 * (Jy - ((sb >> 1) & 1)) + 4 * (Jz - (sb >> 2));
+      const int li = tile_index_block(j, 0) + loff;
+      const T v = tiles[w][0][li];
+      tiles[w][0][li] = T(0);
+      sum += v;
+      sumd += (double)v;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(gl.slot[J]);
+    const int b = __builtin_amdgcn_readfirstlane(gl.bslot[J]);
+    if (s >= 0 && sum != T(0)) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], sum);
+    if (b >= 0 && sumd != 0.0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], sumd);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // grid mass and per-body mass
 // ---------------------------------------------------------------------------
 template <typename T, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
-  __shared__ T tm[G][1][kTileSize];
-  __shared__ T tb[G][1][kTileSize];  // one item's body mass; flushed into FP64
+  __shared__ T tm[G][1][kTileSize];  // one item's mass (shared grid and its body's grid)
   __shared__ GroupLds<G> gl;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   zero_tile<T, 1>(tm[wave]);
-  zero_tile<T, 1>(tb[wave]);
   wave_sync();
   const int64_t n = a.n;
   for (ItemLoop L = item_loop(a, G); L.w < L.end; L.w += L.step) {
@@ -605,66 +661,42 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
     const Item it = member ? mine : a.items[w0];
     const Segment &sg = a.seg[it.seg];
     const bool active = member && lane < it.count;
-    const int64_t i = it.start + (active ? lane : 0);
-    const uint32_t key = a.keys[i];
+    const uint32_t li = active ? lane : 0u;
+    const int64_t i0 = it.start;
+    const uint32_t key = lane_ld(a.keys + i0, li);
     int passes;
     const int rank = cell_rank(active, key & 63u, &passes);
     if (active) {
       T tt[3];
-      load_t(t, n, i, tt);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
       Stencil<T> S;
       make_stencil(tt, (T)a.sc[sg.scene].h, S);
-      const T mp = m[i];
+      const T mp = lane_ld(m + i0, li);
       const int base = particle_base(key);
       for (int pass = 0; pass < passes; ++pass) {
-        if (rank == pass) p2g_mass(&tm[wave][0][0], &tb[wave][0][0], base, S, mp);
+        if (rank == pass) p2g_mass(&tm[wave][0][0], base, S, mp);
         LDS_ORDER();
       }
     }
-    wave_sync();
-    if (member) flush_tile_to<T, double>(tb[wave], g.bmass, sg.bslot);
-    flush_group<T, G, 1>(a, tm, gl, member, it.seg, (T *)g.mass, 1);
+    flush_group_mass<T, G>(a, tm, gl, member, it.seg, (T *)g.mass, g.bmass);
   }
 }
 
 // ---------------------------------------------------------------------------
-// contact normals from the per-body mass grid
+// Contact normals (from the per-body mass grid) and P2G of Vbar into buffer 0
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) void k_normals(StepArgs a, const T *t, T *nrm, GridPtrs g) {
-  __shared__ double tb[1][kTileSize];
-  const int lane = threadIdx.x;
-  const int64_t n = a.n;
-  for (ItemLoop L = item_loop(a); L.w < L.end; L.w += L.step) {
-    const int w = L.w;
-    const Item it = a.items[w];
-    if (it.count == 0) continue;  // run padding
-    const Segment &sg = a.seg[it.seg];
-    const SceneDev &sd = a.sc[sg.scene];
-    if (sd.n_iter == 0) continue;  // no series, normals unused
-    load_tile<double, 1>(tb, g.bmass, sg.bslot, 1);
-    wave_sync();
-    if (lane < it.count) {
-      const int64_t i = it.start + lane;
-      T tt[3];
-      load_t(t, n, i, tt);
-      const double td[3] = {(double)tt[0], (double)tt[1], (double)tt[2]};
-      double nd[3];
-      body_normal(&tb[0][0], particle_base(a.keys[i]), td, sd.h, nd);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) nrm[c * n + i] = (T)nd[c];
-    }
-    wave_sync();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// P2G of Vbar into buffer 0
-// ---------------------------------------------------------------------------
+// Both need the complete mass grids and nothing else of each other, so one
+// pass over the items does both: a wave first stages its item's body-mass
+// tile (FP64) in the space of its P2G tile, computes the normals of its
+// particles, clears that space and then scatters Vbar.  Normals are skipped
+// for scenes without series rounds (unused there).
 template <typename T, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
-void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
-  __shared__ T tq[G][3][kTileSize];
+void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g) {
+  __shared__ __attribute__((aligned(16))) T tq[G][3][kTileSize];
+  static_assert(3 * kTileSize * sizeof(T) >= kTileSize * sizeof(double), "body-mass tile");
+  static_assert((3 * kTileSize * sizeof(T)) % 16 == 0, "tile alignment");
   __shared__ GroupLds<G> gl;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   zero_tile<T, 3>(tq[wave]);
@@ -678,22 +710,42 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, GridPtrs g) {
     const Item it = member ? mine : a.items[w0];
     const Segment &sg = a.seg[it.seg];
     const bool active = member && lane < it.count;
-    const int64_t i = it.start + (active ? lane : 0);
-    const uint32_t key = a.keys[i];
+    const uint32_t li = active ? lane : 0u;
+    const int64_t i0 = it.start;
+    const uint32_t key = lane_ld(a.keys + i0, li);
+    const int base = particle_base(key);
+    const SceneDev &sd = a.sc[sg.scene];
+    T tt[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
+    if (member && sd.n_iter > 0) {  // wave-uniform
+      double(*tb)[kTileSize] = reinterpret_cast<double(*)[kTileSize]>(&tq[wave][0][0]);
+      load_tile<double, 1>(tb, g.bmass, sg.bslot, 1);
+      wave_sync();
+      if (active) {
+        const double td[3] = {(double)tt[0], (double)tt[1], (double)tt[2]};
+        double nd[3];
+        body_normal(&tb[0][0], base, td, sd.h, nd);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lane_st(nrm + c * n + i0, li, (T)nd[c]);
+      }
+      wave_sync();
+      uint4 *z = reinterpret_cast<uint4 *>(&tb[0][0]);
+      for (int k = lane; k < kTileSize * (int)sizeof(double) / 16; k += 64)
+        z[k] = make_uint4(0u, 0u, 0u, 0u);
+      wave_sync();
+    }
     int passes;
     const int rank = cell_rank(active, key & 63u, &passes);
     if (active) {
-      T tt[3];
-      load_t(t, n, i, tt);
       Stencil<T> S;
-      make_stencil(tt, (T)a.sc[sg.scene].h, S);
+      make_stencil(tt, (T)sd.h, S);
       T u[3], E[9];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) u[q] = vbar[q * n + i];
+      for (int q = 0; q < 3; ++q) u[q] = lane_ld(vbar + q * n + i0, li);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) E[q] = vbar[(3 + q) * n + i];
-      const T mp = m[i];
-      const int base = particle_base(key);
+      for (int q = 0; q < 9; ++q) E[q] = lane_ld(vbar + (3 + q) * n + i0, li);
+      const T mp = lane_ld(m + i0, li);
       for (int pass = 0; pass < passes; ++pass) {
         if (rank == pass) p2g(tq[wave], base, S, mp, u, E);
         LDS_ORDER();
@@ -884,14 +936,10 @@ void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStrea
 }
 
 template <typename T>
-void launch_normals(const StepArgs &a, const T *t, T *nrm, GridPtrs g, hipStream_t st) {
-  APIC_LAUNCH((k_normals<T>), dim3(a.item_wg), dim3(64), 0, st, a, t, nrm, g);
-}
-
-template <typename T>
-void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, GridPtrs g,
+void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g,
                  hipStream_t st) {
-#define L_P2G0() APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, g)
+#define L_P2G0() \
+  APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, nrm, g)
   APIC_GROUP_DISPATCH(L_P2G0);
 #undef L_P2G0
 }
@@ -928,9 +976,8 @@ void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, c
 
 #define INST(T)                                                                                 \
   template void launch_mass<T>(const StepArgs &, const T *, const T *, GridPtrs, hipStream_t);  \
-  template void launch_normals<T>(const StepArgs &, const T *, T *, GridPtrs, hipStream_t);     \
-  template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, GridPtrs,     \
-                               hipStream_t);                                                    \
+  template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, T *,         \
+                               GridPtrs, hipStream_t);                                          \
   template void launch_grid_clear<T>(const StepArgs &, GridPtrs, hipStream_t);                 \
   template void launch_iter<T>(const StepArgs &, int, bool, const T *, const T *, const T *,     \
                                const T *, T *, GridPtrs, const uint32_t *, T *, T *,            \
