@@ -275,7 +275,7 @@ def main():
     alg_bytes = n * ROUND_BYTES_PER_PARTICLE["fp32"] + nodes * ROUND_BYTES_PER_NODE["fp32"]
     achieved = alg_bytes / (round_us * 1e-6) / 1e9
     group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
-    round_kernel = f"apic::k_iter<float, false, false, {group}>"
+    round_kernel = f"apic::k_iter<float, false, {group}>"
     traffic = traffic_from_profiles(round_kernel)
     max_drift = drift[0]
     sim.close()

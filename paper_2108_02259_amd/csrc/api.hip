@@ -208,10 +208,11 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.smap_cap = std::max<int64_t>(1, (int64_t)std::ceil(smap_total * headroom));
   P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
   P.seg_cap = std::max<int64_t>(n, 1);
-  // items: at most one per particle plus one per 64, plus the run padding
+  // items: one per segment plus one per 64 particles, plus the run padding
   // (fewer than the group size per run, one run per super block of a body,
-  // and a body's super blocks number 8 block keys each)
-  P.item_cap = n + n / kItem + 1 + kb;
+  // and a body's super blocks number 8 block keys each); segments are
+  // distinct (body, block) keys, so at most min(n, key blocks)
+  P.item_cap = std::min<int64_t>(n, kb) + n / kItem + 1 + kb;
   P.sblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.smap_cap, 8 * n));
   P.bblk_cap = std::max<int64_t>(1, std::min<int64_t>(P.bmap_cap, 8 * n));
   const apic_tuning tu = ctx->tuning_for(P.prec, n);
@@ -249,9 +250,6 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kNrm, T * 3 * n));
   TRY(W.ensure(kY, T * 12 * n));
   TRY(W.ensure(kSeg, sizeof(Segment) * P.seg_cap));
-  TRY(W.ensure(kSegTmp, sizeof(int32_t) * (P.seg_cap + 1)));
-  TRY(W.ensure(kItemOff, sizeof(int32_t) * (P.seg_cap + 1)));
-  TRY(W.ensure(kFlags, sizeof(int32_t) * n));
   TRY(W.ensure(kItems, sizeof(Item) * P.item_cap));
   TRY(W.ensure(kSmark, sizeof(int32_t) * P.smap_cap));
   TRY(W.ensure(kSmap, sizeof(int32_t) * P.smap_cap));
@@ -264,7 +262,7 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kInvM, sizeof(double) * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kBMass, sizeof(double) * kNodesPerBlock * P.bblk_cap));
   TRY(W.ensure(kRecGather, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
-  TRY(W.ensure(kRecItems, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
+  TRY(W.ensure(kRecItems, sizeof(RedRec) * P.item_cap));  // one per work item
   P.rec_gather = (RedRec *)W.ptr[kRecGather];
   P.rec_items = (RedRec *)W.ptr[kRecItems];
   P.ka = (uint32_t *)W.ptr[kKeysA];
@@ -275,7 +273,6 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.lb.flags = (uint64_t *)W.ptr[kLbFlags];
   P.lb.capacity = (int64_t)(W.size[kLbFlags] / sizeof(uint64_t));
   P.lb.state = (uint32_t *)W.ptr[kLbState];
-  P.item_off = (int32_t *)W.ptr[kItemOff];
   P.smark = (int32_t *)W.ptr[kSmark];
   P.bmark = (int32_t *)W.ptr[kBmark];
   P.t = W.ptr[kT];
@@ -284,8 +281,6 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.nrm = W.ptr[kNrm];
   P.Y = W.ptr[kY];
   P.seg = (Segment *)W.ptr[kSeg];
-  P.segtmp = (int32_t *)W.ptr[kSegTmp];
-  P.flags = (int32_t *)W.ptr[kFlags];
   P.items = (Item *)W.ptr[kItems];
   P.smap = (int32_t *)W.ptr[kSmap];
   P.bmap = (int32_t *)W.ptr[kBmap];
@@ -313,8 +308,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
 template <typename T>
 static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
                            const int32_t *sticky, bool check_caps) {
-  launch_layout_init(P.sacc, P.ns, P.bacc, (int)P.nb_cap, P.cnt, st);
-  if (sticky) launch_copy_sticky(P.cnt, sticky, st);
+  launch_layout_init(P.sacc, P.ns, P.bacc, (int)P.nb_cap, P.cnt, sticky, P.red,
+                     (int64_t)kRed * 2 * P.ns, st);
   launch_cells<T>(x, body, P.n, P.sc, P.ns, P.bacc, P.box_rec, P.cnt, st);
   launch_reduce_box(P.box_rec, wave_records(P.n), P.bacc, st);
   launch_domains(P.sc, P.ns, (int)P.nb_cap, P.sacc, P.bacc, P.slay, P.blay, P.cnt,
@@ -331,10 +326,10 @@ static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *
 template <typename T>
 static void enqueue_sort(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
                          Profiler *prof, bool full_key = false) {
-  launch_keys<T>(x, body, P.n, P.sc, P.ns, P.blay, P.ka, st);
+  const int lo = full_key ? 0 : 6;
+  launch_keys<T>(x, body, P.n, P.sc, P.ns, P.blay, P.ka, lo, P.ghist, st);
   if (prof) prof->end(APIC_KC_LAYOUT, st), prof->begin(st);
-  int where = radix_sort(P.ka, P.va, P.kb, P.vb, P.n, full_key ? 0 : 6, P.sort_bits, P.ghist,
-                         P.lb, st);
+  int where = radix_sort(P.ka, P.va, P.kb, P.vb, P.n, lo, P.sort_bits, P.ghist, P.lb, true, st);
   if (prof) prof->end(APIC_KC_SORT, st);
   P.keys = where ? P.kb : P.ka;
   P.perm = where ? P.vb : P.va;
@@ -350,7 +345,6 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
                          T *v_out, T *C_out, bool unpermute, Profiler *prof) {
   const int64_t n = P.n;
   if (prof) prof->begin(st);
-  fill_bytes_zero(P.red, sizeof(double) * kRed * 2 * P.ns, st);
   // the gather also orders each wave's particles by cell within a block, and
   // writes that order's keys and permutation into the sort's free buffers
   uint32_t *keys2 = P.keys == P.ka ? P.kb : P.ka;
@@ -362,10 +356,10 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   P.perm = perm2;
   launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
-  launch_segments(P.keys, n, P.flags, P.lb, P.tot, P.sbody, P.blay, P.seg, P.seg_cap, P.items,
-                  P.item_cap, P.segtmp, P.item_off, P.group, P.cnt, st);
+  launch_segments(P.keys, n, P.lb, P.tot, P.sbody, P.blay, P.slay, P.seg, P.seg_cap, P.items,
+                  P.item_cap, P.smark, P.smap_cap, P.bmark, P.bmap_cap, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
-              P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, st);
+              P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, P.item_cap, st);
   StepArgs a;
   a.sc = P.sc;
   a.seg = P.seg;
@@ -387,18 +381,19 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   launch_p2g0<T>(a, t, m_sorted, vbar, nrm, P.g, st);
   if (prof) prof->end(APIC_KC_P2G0, st);
   const uint32_t *perm_out = unpermute ? P.perm : nullptr;
-  for (int k = 1; k <= P.max_iter + 1; ++k) {
-    const bool final = k == P.max_iter + 1;
+  for (int k = 1; k <= P.max_iter; ++k) {
     if (prof) prof->begin(st);
-    launch_iter<T>(a, k, final, t, m_sorted, vbar, nrm, Y, P.g, perm_out, v_out, C_out, st);
-    if (prof) prof->end(final ? APIC_KC_FINAL : (k == 1 ? APIC_KC_ROUND1 : APIC_KC_ROUND), st);
+    launch_round<T>(a, k, t, m_sorted, vbar, nrm, Y, P.g, perm_out, v_out, C_out, st);
+    if (prof) prof->end(k == 1 ? APIC_KC_ROUND1 : APIC_KC_ROUND, st);
   }
-  // momentum after (FP64) and, for the resident driver, the drift
+  // the last round also takes the FP64 momentum after the step and, for the
+  // resident driver, the drift (positions at the output index)
   if (prof) prof->begin(st);
   T *x_after = unpermute ? (T *)x : x_sorted;
-  launch_after<T>(n, perm_out, x_after, v_out, C_out, m_sorted, nrm, P.sbody, P.blay, P.sc, P.cnt,
-                  unpermute ? 0 : 1, P.rec_items, P.red + kRed * P.ns, st);
-  launch_reduce_red(P.rec_items, wave_records(n), nullptr, P.cnt, P.red + kRed * P.ns, st);
+  launch_final<T>(a, P.max_iter + 1, t, m_sorted, vbar, nrm, Y, P.g, perm_out, v_out, C_out,
+                  x_after, unpermute ? 0 : 1, P.rec_items, st);
+  if (prof) prof->end(APIC_KC_FINAL, st), prof->begin(st);
+  launch_reduce_red(P.rec_items, P.item_cap, &P.cnt->n_items, P.cnt, P.red + kRed * P.ns, st);
   if (prof) prof->end(APIC_KC_AFTER, st);
 }
 
@@ -751,11 +746,13 @@ int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec
   const int64_t tb = prec == APIC_FP64 ? 8 : 4;
   if (blocks_hint <= 0) blocks_hint = n / 16 + 64;
   // resident state x2 (x, vC, m, body, orig), sorted scratch (t, m, normals,
-  // series), keys/values x2, segment/item tables; grid mass, 3 momentum
-  // buffers, 1/m and per-body mass per node block.
+  // series), keys/values x2, segment table; work items and their reduction
+  // records (one per 64 particles plus about two per block); grid mass, 3
+  // momentum buffers, 1/m and per-body mass per node block.
+  const int64_t per_item = (int64_t)(sizeof(Item) + sizeof(RedRec));
   int64_t per_particle = 2 * (tb * 16 + 2 + 4) + tb * (3 + 1 + 3 + 12) + 4 * 5 + 16 +
-                         (int64_t)sizeof(Segment) + 2 * (int64_t)sizeof(Item);
-  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2;
+                         (int64_t)sizeof(Segment) + per_item / kItem + 1;
+  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2 + 2 * per_item;
   return n * per_particle + blocks_hint * per_block + (1 << 20);
 }
 

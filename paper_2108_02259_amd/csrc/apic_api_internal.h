@@ -30,8 +30,8 @@ namespace apic {
 
 enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
-  kValsB, kGhist, kLbFlags, kLbState, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg, kSegTmp,
-  kItemOff, kFlags, kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kGBuf2, kInvM, kBMass,
+  kValsB, kGhist, kLbFlags, kLbState, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg,
+  kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kGBuf2, kInvM, kBMass,
   kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
 };
 
@@ -79,7 +79,6 @@ struct Plan {
   void *t = nullptr, *ms = nullptr, *nrm = nullptr, *Y = nullptr;
   int32_t *sbody = nullptr;
   Segment *seg = nullptr;
-  int32_t *segtmp = nullptr, *item_off = nullptr, *flags = nullptr;
   Item *items = nullptr;
   int32_t *smark = nullptr, *smap = nullptr, *bmark = nullptr, *bmap = nullptr;
   GridPtrs g = {};
@@ -122,7 +121,6 @@ struct SimDev {
 };
 
 // ---- driver kernels (misc.hip) --------------------------------------------
-void launch_copy_sticky(Counters *cnt, const int32_t *sticky, hipStream_t st);
 void launch_clear_sticky(SimDev *dev, hipStream_t st);
 void launch_step_end(const Counters *cnt, const double *red, int ns, SimDev *dev, double *drift,
                      hipStream_t st);

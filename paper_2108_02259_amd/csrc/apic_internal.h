@@ -173,6 +173,35 @@ __device__ __forceinline__ int tile_index_block(int j, int n) {
 
 __device__ __forceinline__ int floor_div4(int c) { return c >> 2; }  // arithmetic shift
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
+// particle count, unconstrained count (filled elsewhere).
+__device__ __forceinline__ void momentum_terms(const double r[3], const double v[3],
+                                               const double C[9], double m, double h,
+                                               double q[kRed]) {
+  const double k = 0.5 * h * h;
+  q[0] = m * v[0];
+  q[1] = m * v[1];
+  q[2] = m * v[2];
+  q[3] = m * (r[1] * v[2] - r[2] * v[1] + k * (C[7] - C[5]));
+  q[4] = m * (r[2] * v[0] - r[0] * v[2] + k * (C[2] - C[6]));
+  q[5] = m * (r[0] * v[1] - r[1] * v[0] + k * (C[3] - C[1]));
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  double c2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) c2 += C[a] * C[a];
+  q[6] = 0.5 * m * (v2 + k * c2);
+  q[7] = m * sqrt(v2);
+  q[8] = m * (sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * sqrt(v2) + k * sqrt(c2));
+  q[9] = 1.0;
+  q[10] = 0.0;
+}
+
 // Binary search: the scene whose [offset, offset+count) holds particle p.
 __device__ __forceinline__ int scene_of(const SceneDev *sc, int ns, int64_t p) {
   int lo = 0, hi = ns - 1;

@@ -29,10 +29,6 @@ void lookback_init(const Lookback &lb, hipStream_t st);
 // written to *total (int64).  mode 1 writes -1 where in[i] == 0 (slot maps).
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_t *n_dev,
                     int64_t *total, const Lookback &lb, int mode, hipStream_t st);
-// Segment number of every sorted particle (exclusive scan of "a new 4x4x4
-// block starts here" flags, computed from the keys), total segments to *total.
-void scan_segment_heads(const uint32_t *keys, int32_t *seg_id, int64_t n, int64_t *total,
-                        const Lookback &lb, hipStream_t st);
 
 void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, int64_t scale,
               hipStream_t st);
@@ -55,8 +51,10 @@ inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 // permutation 0..n-1 (va need not be initialised).  hist holds
 // radix_hist_words(n) words of scratch.
 inline int64_t radix_hist_words(int64_t n) { return 2 * 256 * sort_tiles(n) + 4; }
+// hist0_ready: the first pass's digit counts are already in hist (written by
+// launch_keys with the sort's tile geometry).
 int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n, int lo,
-               int bits, uint32_t *hist, const Lookback &lb, hipStream_t st);
+               int bits, uint32_t *hist, const Lookback &lb, bool hist0_ready, hipStream_t st);
 
 // ---- layout (layout.hip) ---------------------------------------------------
 // One box record per wavefront (rec has ceil(n/256)*4 entries), then reduced.
@@ -64,16 +62,20 @@ template <typename T>
 void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
                   BodyAcc *bacc, BoxRec *rec, Counters *cnt, hipStream_t st);
 inline int64_t wave_records(int64_t n) { return (n + 255) / 256 * 4; }
+// Empty boxes, zero counters (error word from sticky if given) and cleared
+// per-scene sums red[0, red_n).
 void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
-                        hipStream_t st);
+                        const int32_t *sticky, double *red, int64_t red_n, hipStream_t st);
 // key_bits > 0: flag kErrResize if the key space needs more bits; smap_cap /
 // bmap_cap > 0: flag kErrResize if the node-block maps need more entries.
 void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, const BodyAcc *bacc,
                     SceneLay *slay, BodyLay *blay, Counters *cnt, int key_bits, int64_t smap_cap,
                     int64_t bmap_cap, hipStream_t st);
+// Cell keys; also the digit counts of the sort's first pass (bits
+// [shift, shift+8)) per sort tile into hist, as the radix sort lays them out.
 template <typename T>
 void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                 const BodyLay *blay, uint32_t *keys, hipStream_t st);
+                 const BodyLay *blay, uint32_t *keys, int shift, uint32_t *hist, hipStream_t st);
 // Gather the particle state into sorted order.  keys/perm come from the
 // block-order sort; within each wave the particles are further ordered by
 // cell (stable), and that final order's keys and permutation go to
@@ -85,18 +87,21 @@ void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const 
                    T *x_out, uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
                    uint32_t *keys_out, uint32_t *perm_out, RedRec *rec, double *direct,
                    hipStream_t st);
-void launch_segments(const uint32_t *keys, int64_t n, int32_t *seg_id, const Lookback &lb,
-                     int64_t *tot, const int32_t *sbody, const BodyLay *blay,
-                     Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap,
-                     int32_t *seg_tmp, int32_t *item_off, int align, Counters *cnt,
+// Segments (one per (body, cell block) of the sorted keys, with their node
+// blocks marked in smark/bmark) and work items, from two single-pass scans;
+// tot[0] = segments, tot[1] = items, tot[5]/tot[6] = slot-map extents.
+void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_t *tot,
+                     const int32_t *sbody, const BodyLay *blay, const SceneLay *slay,
+                     Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap, int32_t *smark,
+                     int64_t smap_cap, int32_t *bmark, int64_t bmap_cap, int align, Counters *cnt,
                      hipStream_t st);
-// Node-block maps: mark the blocks every segment touches, scan the marks into
-// slots, store each segment's 8 slots and clear the marks again (so that the
-// mark arrays are all zero between steps).
+// Node-block maps: scan the marks into slots, store each segment's 8 slots
+// and clear the marks again (so that the mark arrays are all zero between
+// steps); publishes the segment, item and active-block counts.
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
-                 int64_t sblk_cap, int64_t bblk_cap, hipStream_t st);
+                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, hipStream_t st);
 
 // ---- transfers (transfer.hip) ---------------------------------------------
 struct GridPtrs {
@@ -131,22 +136,22 @@ void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nr
 // the active blocks (counts on the device).
 template <typename T>
 void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st);
-// One fused round k >= 1: G2P of the momenta in buffer (k-1) mod 3 (turned
-// into velocities q/m as the tile is loaded), the rule, P2G of the next series
-// field into buffer k mod 3, and clearing of buffer (k+1) mod 3 for round
-// k+1.  Scenes whose n_iter == k-1 finish here (writing Vhat to v_out/C_out at
-// perm[i], or at i when perm is null).  `final` selects the finishing-only
-// kernel (k = max n_iter + 1).
+// One fused round k = 1 .. max n_iter: G2P of the momenta in buffer
+// (k-1) mod 3 (turned into velocities q/m as the tile is loaded), the rule,
+// P2G of the next series field into buffer k mod 3, and clearing of buffer
+// (k+1) mod 3 for round k+1.  Scenes whose n_iter == k-1 finish here (writing
+// Vhat to v_out/C_out at perm[i], or at i when perm is null).
 template <typename T>
-void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
-                 const T *nrm, T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out,
-                 hipStream_t st);
-// FP64 momentum after the step (+ the resident driver's drift).
+void launch_round(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
+                  T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, hipStream_t st);
+// The last round k = max n_iter + 1: the remaining scenes finish, then every
+// particle's FP64 momentum after the step (one record per work item into
+// rec, item_cap entries) and, with drift set, x += dt v (x indexed like
+// v_out).
 template <typename T>
-void launch_after(int64_t n, const uint32_t *perm, T *x, const T *v, const T *C,
-                  const T *m_sorted, const T *nrm, const int32_t *sbody, const BodyLay *blay,
-                  const SceneDev *sc, const Counters *cnt, int apply_drift, RedRec *rec,
-                  double *direct, hipStream_t st);
+void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
+                  const T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, T *x,
+                  int drift, RedRec *rec, hipStream_t st);
 // Reduce records [0, count) (count = *count_dev if non-null, skipped when the
 // step has an error) into out[key * kRed + c].
 void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *count_dev,

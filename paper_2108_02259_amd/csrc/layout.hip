@@ -6,7 +6,9 @@
 // bit for bit on the cell, hence on keys and order.
 #include <climits>
 
-#include "kernels.h"
+#include <algorithm>
+
+#include "scan.h"
 
 namespace apic {
 
@@ -54,8 +56,12 @@ __device__ __forceinline__ void wave_minmax3(int32_t mn[3], int32_t mx[3]) {
     }
 }
 
-__global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Start of a step's layout: empty scene and body boxes, zero counters (the
+// error word taken from `sticky` when given), and the per-scene reduction
+// sums cleared (red_n doubles).
+__global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
+                              const int32_t *sticky, double *red, int64_t red_n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ns) {
     for (int d = 0; d < 3; ++d) {
       sacc[i].bmin[d] = INT_MAX;
@@ -68,17 +74,19 @@ __global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap,
       bacc[i].bmin[d] = INT_MAX;
       bacc[i].bmax[d] = INT_MIN;
     }
+  if (i < red_n) red[i] = 0.0;
   if (i == 0) {
     Counters z = {};
+    if (sticky) z.err = *sticky;
     *cnt = z;
   }
 }
 
 void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
-                        hipStream_t st) {
-  int64_t m = ns > nb_cap ? ns : nb_cap;
-  if (m < 1) m = 1;
-  APIC_LAUNCH(k_layout_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, sacc, ns, bacc, nb_cap, cnt);
+                        const int32_t *sticky, double *red, int64_t red_n, hipStream_t st) {
+  int64_t m = std::max<int64_t>({(int64_t)ns, (int64_t)nb_cap, red_n, (int64_t)1});
+  APIC_LAUNCH(k_layout_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, sacc, ns, bacc,
+              nb_cap, cnt, sticky, red, red_n);
 }
 
 // Cells of every particle; each wavefront emits one record with the block box
@@ -342,11 +350,9 @@ void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, cons
 // keys
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_keys(const T *x, const uint16_t *body, int64_t n,
-                                              const SceneDev *sc, int ns, const BodyLay *blay,
-                                              uint32_t *keys) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+__device__ __forceinline__ uint32_t cell_key(const T *x, const uint16_t *body, int64_t n,
+                                            int64_t p, const SceneDev *sc, int ns,
+                                            const BodyLay *blay) {
   const int s = scene_of(sc, ns, p);
   const SceneDev sd = sc[s];
   CellInfo ci = cell_of(x, n, p, sd);
@@ -366,25 +372,49 @@ __global__ __launch_bounds__(256) void k_keys(const T *x, const uint16_t *body, 
     int cib = (ci.c[0] & 3) | ((ci.c[1] & 3) << 2) | ((ci.c[2] & 3) << 4);
     if (lin < kMaxKeyBlocks) key = (uint32_t)(lin * 64 + cib);
   }
-  keys[p] = key;
+  return key;
+}
+
+// Keys in the radix sort's tile geometry (kSortItems keys per thread), with
+// the first pass's per-tile digit counts (digit-major, as the sort lays them
+// out), so that the sort starts at its first scan.
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_keys(const T *x, const uint16_t *body, int64_t n,
+                                                       const SceneDev *sc, int ns,
+                                                       const BodyLay *blay, uint32_t *keys,
+                                                       int ntiles, int shift, uint32_t *hist) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x, t = blockIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const int64_t tbase = (int64_t)t * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t p = tbase + (int64_t)r * kSortThreads + tid;
+    const bool ok = p < n;
+    uint32_t key = 0;
+    if (ok) {
+      key = cell_key(x, body, n, p, sc, ns, blay);
+      keys[p] = key;
+    }
+    count_digit(h, ok, (key >> shift) & 255u);
+  }
+  __syncthreads();
+  hist[(int64_t)tid * ntiles + t] = h[tid];
 }
 
 template <typename T>
 void launch_keys(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                 const BodyLay *blay, uint32_t *keys, hipStream_t st) {
+                 const BodyLay *blay, uint32_t *keys, int shift, uint32_t *hist, hipStream_t st) {
   if (n <= 0) return;
-  APIC_LAUNCH((k_keys<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, body, n, sc, ns, blay, keys);
+  const int64_t ntiles = sort_tiles(n);
+  APIC_LAUNCH((k_keys<T>), dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, x, body, n, sc, ns,
+              blay, keys, (int)ntiles, shift, hist);
 }
 
 // ---------------------------------------------------------------------------
 // gather into sorted order (+ momentum before)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // One record per wavefront of per-scene sums (when the wave is uniform in
 // scene; per-lane atomics into `direct` otherwise).
 __device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed], RedRec *rec,
@@ -409,29 +439,6 @@ __device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed
     }
   }
   if (lane == 0) rec[wave].key = key;
-}
-
-// P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
-// particle count, unconstrained count (filled elsewhere).
-__device__ __forceinline__ void momentum_terms(const double r[3], const double v[3],
-                                               const double C[9], double m, double h,
-                                               double q[kRed]) {
-  const double k = 0.5 * h * h;
-  q[0] = m * v[0];
-  q[1] = m * v[1];
-  q[2] = m * v[2];
-  q[3] = m * (r[1] * v[2] - r[2] * v[1] + k * (C[7] - C[5]));
-  q[4] = m * (r[2] * v[0] - r[0] * v[2] + k * (C[2] - C[6]));
-  q[5] = m * (r[0] * v[1] - r[1] * v[0] + k * (C[3] - C[1]));
-  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  double c2 = 0.0;
-#pragma unroll
-  for (int a = 0; a < 9; ++a) c2 += C[a] * C[a];
-  q[6] = 0.5 * m * (v2 + k * c2);
-  q[7] = m * sqrt(v2);
-  q[8] = m * (sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * sqrt(v2) + k * sqrt(c2));
-  q[9] = 1.0;
-  q[10] = 0.0;
 }
 
 // Position of this lane's particle once the 64 sorted particles of its wave
@@ -531,191 +538,19 @@ void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const 
               orig_in, orig_out, keys_out, perm_out, rec, direct);
 }
 
-// Momentum after the contact step (and the drift x += dt v of the resident
-// driver).  Sorted index i; the result lives at perm[i] (caller order) when
-// perm is given, else at i (resident sorted state).  The momentum uses the
-// positions before the drift.
-template <typename T>
-__global__ __launch_bounds__(256) void k_after(int64_t n, const uint32_t *perm, T *x, const T *v,
-                                               const T *C, const T *m_sorted, const T *nrm,
-                                               const int32_t *sbody, const BodyLay *blay,
-                                               const SceneDev *sc, const Counters *cnt,
-                                               int apply_drift, RedRec *rec, double *direct) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = i < n && cnt->err == 0;
-  int s = 0;
-  double q[kRed];
-  if (ok) {
-    const int64_t p = perm ? (int64_t)perm[i] : i;
-    s = blay[sbody[i]].scene;
-    const SceneDev &sd = sc[s];
-    double r[3], vv[3], CC[9];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      vv[d] = (double)v[d * n + p];
-      r[d] = (double)x[d * n + p] - sd.origin[d];
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) CC[k] = (double)C[k * n + p];
-    momentum_terms(r, vv, CC, (double)m_sorted[i], sd.h, q);
-    q[10] = (sd.n_iter > 0 && nrm && nrm[i] == T(0) && nrm[n + i] == T(0) && nrm[2 * n + i] == T(0))
-                ? 1.0 : 0.0;
-    if (apply_drift)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) x[d * n + p] = x[d * n + p] + (T)(sd.dt * vv[d]);
-  }
-  reduce_scene(ok, s, q, rec, i >> 6, direct);
-}
-
-template <typename T>
-void launch_after(int64_t n, const uint32_t *perm, T *x, const T *v, const T *C,
-                  const T *m_sorted, const T *nrm, const int32_t *sbody, const BodyLay *blay,
-                  const SceneDev *sc, const Counters *cnt, int apply_drift, RedRec *rec,
-                  double *direct, hipStream_t st) {
-  if (n <= 0) return;
-  APIC_LAUNCH((k_after<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm, x, v, C, m_sorted, nrm, sbody,
-                                                           blay, sc, cnt, apply_drift, rec,
-                                                           direct);
-}
-
-template void launch_after<float>(int64_t, const uint32_t *, float *, const float *,
-                                  const float *, const float *, const float *, const int32_t *,
-                                  const BodyLay *, const SceneDev *, const Counters *, int,
-                                  RedRec *, double *, hipStream_t);
-template void launch_after<double>(int64_t, const uint32_t *, double *, const double *,
-                                   const double *, const double *, const double *,
-                                   const int32_t *, const BodyLay *, const SceneDev *,
-                                   const Counters *, int, RedRec *, double *, hipStream_t);
-
 // ---------------------------------------------------------------------------
 // segments and work items
 // ---------------------------------------------------------------------------
 
-// flags have been scanned in place into seg ids; heads write segments.
-__global__ void k_seg_heads(const uint32_t *keys, int64_t n, const int32_t *segid,
-                            const int32_t *sbody, const BodyLay *blay, Segment *seg,
-                            int64_t seg_cap, Counters *cnt) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    bool head = i == 0 || (keys[i] >> 6) != (keys[i - 1] >> 6);
-    if (!head) continue;
-    int32_t k = segid[i];
-    if (k >= seg_cap) {
-      atomicOr(&cnt->err, kErrCapacity);
-      continue;
-    }
-    const int gb = sbody[i];
-    const BodyLay bl = blay[gb];
-    const int64_t local = (int64_t)(keys[i] >> 6) - bl.key_off;
-    const int sub = (int)(local & 7);
-    const int64_t sl = local >> 3;
-    const int ex = bl.kext[0] > 0 ? bl.kext[0] : 1, ey = bl.kext[1] > 0 ? bl.kext[1] : 1;
-    const int lx = 2 * (bl.kmin[0] + (int)(sl % ex)) + (sub & 1) - bl.bmin[0];
-    const int ly = 2 * (bl.kmin[1] + (int)((sl / ex) % ey)) + ((sub >> 1) & 1) - bl.bmin[1];
-    const int lz = 2 * (bl.kmin[2] + (int)(sl / ((int64_t)ex * ey))) + ((sub >> 2) & 1) - bl.bmin[2];
-    Segment sg;
-    sg.start = (int32_t)i;
-    sg.count = 0;
-    sg.body = gb;
-    sg.scene = bl.scene;
-    sg.B[0] = bl.bmin[0] + lx;
-    sg.B[1] = bl.bmin[1] + ly;
-    sg.B[2] = bl.bmin[2] + lz;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      sg.sslot[j] = -1;
-      sg.bslot[j] = -1;
-    }
-    seg[k] = sg;
-  }
-}
+// The segment tables come from two single-pass scans.  The first runs over
+// the sorted particles: a particle whose block key differs from its
+// predecessor's starts a segment, and the scan's output step writes that
+// segment (start, body, scene, block) at its index and marks the 8 shared and
+// 8 body node blocks it touches.  The second runs over the segments: each
+// contributes its work items (one per 64 particles, plus the run padding on
+// the last segment of a run), and the output step writes its particle count
+// and its items.
 
-// counts from consecutive starts; items per segment into tmp.
-// Segments of one body whose blocks lie in one 2x2x2 super block (a run: at
-// most 8 consecutive segments, one per block).
-__device__ __forceinline__ bool same_run(const Segment &a, const Segment &b) {
-  return a.body == b.body && (a.B[0] >> 1) == (b.B[0] >> 1) && (a.B[1] >> 1) == (b.B[1] >> 1) &&
-         (a.B[2] >> 1) == (b.B[2] >> 1);
-}
-
-__device__ __forceinline__ int32_t seg_items(const Segment *seg, int64_t k, int64_t ns, int64_t n) {
-  const int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
-  return (int32_t)((end - seg[k].start + kItem - 1) / kItem);
-}
-
-// Particle count and item count of every segment; the last segment of a run
-// also takes the run's padding items.
-__global__ void k_seg_counts(Segment *seg, int64_t seg_cap, const int64_t *nseg_dev, int64_t n,
-                             int align, int32_t *nitems, Counters *cnt) {
-  int64_t ns = *nseg_dev;
-  if (ns > seg_cap) ns = seg_cap;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const Segment sk = seg[k];
-    int64_t end = (k + 1 < ns) ? seg[k + 1].start : n;
-    seg[k].count = (int32_t)(end - sk.start);
-    int32_t items = seg_items(seg, k, ns, n);
-    if (align > 1 && (k + 1 == ns || !same_run(seg[k + 1], sk))) {
-      int32_t run = items;
-      for (int64_t h = k - 1; h >= 0 && k - h < 8 && same_run(seg[h], sk); --h)
-        run += seg_items(seg, h, ns, n);
-      items += (align - run % align) % align;
-    }
-    nitems[k] = items;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_seg = (int32_t)ns;
-}
-
-__global__ void k_items(const Segment *seg, int64_t seg_cap, const int64_t *nseg_dev,
-                        const int32_t *item_off, Item *items, int64_t item_cap, Counters *cnt,
-                        const int64_t *nitems_dev) {
-  int64_t ns = *nseg_dev;
-  if (ns > seg_cap) ns = seg_cap;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const Segment sg = seg[k];
-    const int64_t off = item_off[k];
-    const int64_t end = (k + 1 < ns) ? (int64_t)item_off[k + 1] : *nitems_dev;
-    // real items, then (last segment of a run) empty padding items
-    for (int64_t w = off; w < end; ++w) {
-      if (w >= item_cap) {
-        atomicOr(&cnt->err, kErrCapacity);
-        break;
-      }
-      const int32_t s = (int32_t)(w - off) * kItem;
-      Item it;
-      it.seg = (int32_t)k;
-      it.start = sg.start + (s < sg.count ? s : 0);
-      it.count = s < sg.count ? min(kItem, sg.count - s) : 0;
-      it.pad = 0;
-      items[w] = it;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int64_t w = *nitems_dev;
-    cnt->n_items = (int32_t)(w < item_cap ? w : item_cap);
-  }
-}
-
-void launch_segments(const uint32_t *keys, int64_t n, int32_t *seg_id, const Lookback &lb,
-                     int64_t *tot, const int32_t *sbody, const BodyLay *blay, Segment *seg,
-                     int64_t seg_cap, Item *items, int64_t item_cap, int32_t *seg_tmp,
-                     int32_t *item_off, int align, Counters *cnt, hipStream_t st) {
-  if (n <= 0) return;
-  unsigned g = (unsigned)((n + 255) / 256);
-  if (g > 8192) g = 8192;
-  scan_segment_heads(keys, seg_id, n, &tot[0], lb, st);
-  APIC_LAUNCH(k_seg_heads, dim3(g), dim3(256), 0, st, keys, n, seg_id, sbody, blay, seg, seg_cap, cnt);
-  unsigned gs = (unsigned)((seg_cap + 255) / 256);
-  if (gs > 8192) gs = 8192;
-  APIC_LAUNCH(k_seg_counts, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], n, align, seg_tmp, cnt);
-  scan_exclusive(seg_tmp, item_off, seg_cap, &tot[0], &tot[1], lb, 0, st);
-  APIC_LAUNCH(k_items, dim3(gs), dim3(256), 0, st, seg, seg_cap, &tot[0], item_off, items, item_cap, cnt, &tot[1]);
-}
-
-// ---------------------------------------------------------------------------
-// node-block maps
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t smap_index(const SceneLay &L, int bx, int by, int bz) {
   int rx = bx - L.smin[0], ry = by - L.smin[1], rz = bz - L.smin[2];
   return L.smap_off + rx + (int64_t)L.sext[0] * (ry + (int64_t)L.sext[1] * rz);
@@ -727,36 +562,155 @@ __device__ __forceinline__ int64_t bmap_index(const BodyLay &L, int bx, int by, 
   return L.bmap_off + rx + ex * (ry + ey * rz);
 }
 
-__global__ void k_mark(const Segment *seg, const Counters *cnt, int64_t seg_cap,
-                       const SceneLay *slay, const BodyLay *blay, int32_t *smark, int64_t smap_cap,
-                       int32_t *bmark, int64_t bmap_cap, int64_t *tot) {
-  int64_t ns = cnt->n_seg;
-  if (ns > seg_cap) ns = seg_cap;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    tot[5] = cnt->smap_total;
-    tot[6] = cnt->bmap_total;
+// 1 where a new (body, 4x4x4 block) segment starts in the sorted keys.
+struct SegHeadIn {
+  const uint32_t *keys;
+  __device__ __forceinline__ int operator()(int64_t i, int64_t) const {
+    return (i == 0 || (keys[i] >> 6) != (keys[i - 1] >> 6)) ? 1 : 0;
   }
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = q >> 3;
-    const int j = (int)(q & 7);
-    const Segment &sg = seg[k];
-    const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
-    int64_t si = smap_index(slay[sg.scene], bx, by, bz);
-    int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
-    if (si >= 0 && si < smap_cap) smark[si] = 1;
-    if (bi >= 0 && bi < bmap_cap) bmark[bi] = 1;
+};
+
+struct SegHeadOut {
+  const uint32_t *keys;
+  const int32_t *sbody;
+  const BodyLay *blay;
+  const SceneLay *slay;
+  Segment *seg;
+  int64_t seg_cap;
+  int32_t *smark, *bmark;
+  int64_t smap_cap, bmap_cap;
+  Counters *cnt;
+  int64_t *tot;
+  __device__ void operator()(int64_t i, int head, int k, int64_t) const {
+    if (i == 0) {  // slot-map extents for the map scans
+      tot[5] = cnt->smap_total;
+      tot[6] = cnt->bmap_total;
+    }
+    if (!head) return;
+    if (k >= seg_cap) {
+      atomicOr(&cnt->err, kErrCapacity);
+      return;
+    }
+    const uint32_t key = keys[i];
+    const int gb = sbody[i];
+    const BodyLay bl = blay[gb];
+    const int64_t local = (int64_t)(key >> 6) - bl.key_off;
+    const int sub = (int)(local & 7);
+    const int64_t sl = local >> 3;
+    const int ex = bl.kext[0] > 0 ? bl.kext[0] : 1, ey = bl.kext[1] > 0 ? bl.kext[1] : 1;
+    Segment sg;
+    sg.start = (int32_t)i;
+    sg.count = 0;
+    sg.body = gb;
+    sg.scene = bl.scene;
+    sg.B[0] = 2 * (bl.kmin[0] + (int)(sl % ex)) + (sub & 1);
+    sg.B[1] = 2 * (bl.kmin[1] + (int)((sl / ex) % ey)) + ((sub >> 1) & 1);
+    sg.B[2] = 2 * (bl.kmin[2] + (int)(sl / ((int64_t)ex * ey))) + ((sub >> 2) & 1);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sg.sslot[j] = -1;
+      sg.bslot[j] = -1;
+    }
+    seg[k] = sg;
+    const SceneLay sl_ = slay[bl.scene];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
+      const int64_t si = smap_index(sl_, bx, by, bz);
+      const int64_t bi = bmap_index(bl, bx, by, bz);
+      if (si >= 0 && si < smap_cap) smark[si] = 1;
+      if (bi >= 0 && bi < bmap_cap) bmark[bi] = 1;
+    }
   }
+};
+
+// Segments of one body whose blocks lie in one 2x2x2 super block (a run: at
+// most 8 consecutive segments, one per block).  Reads the fields the first
+// scan wrote (never count, which the second scan's output step writes).
+__device__ __forceinline__ bool same_run(const Segment *seg, int64_t a, int64_t b) {
+  return seg[a].body == seg[b].body && (seg[a].B[0] >> 1) == (seg[b].B[0] >> 1) &&
+         (seg[a].B[1] >> 1) == (seg[b].B[1] >> 1) && (seg[a].B[2] >> 1) == (seg[b].B[2] >> 1);
 }
 
+__device__ __forceinline__ int64_t seg_end(const Segment *seg, int64_t k, int64_t ns,
+                                           int64_t np) {
+  return (k + 1 < ns) ? seg[k + 1].start : np;
+}
+
+// Work items of segment k: one per 64 particles; the last segment of a run
+// also takes the run's padding to a multiple of `align`.
+struct SegItemsIn {
+  const Segment *seg;
+  int64_t np;
+  int align;
+  __device__ int operator()(int64_t k, int64_t ns) const {
+    int32_t items = (int32_t)((seg_end(seg, k, ns, np) - seg[k].start + kItem - 1) / kItem);
+    if (align > 1 && (k + 1 == ns || !same_run(seg, k + 1, k))) {
+      int32_t run = items;
+      for (int64_t h = k - 1; h >= 0 && k - h < 8 && same_run(seg, h, k); --h)
+        run += (int32_t)((seg_end(seg, h, ns, np) - seg[h].start + kItem - 1) / kItem);
+      items += (align - run % align) % align;
+    }
+    return items;
+  }
+};
+
+struct ItemsOut {
+  Segment *seg;
+  int64_t np;
+  Item *items;
+  int64_t item_cap;
+  Counters *cnt;
+  __device__ void operator()(int64_t k, int n_items, int off, int64_t ns) const {
+    const int32_t start = seg[k].start;
+    const int32_t count = (int32_t)(seg_end(seg, k, ns, np) - start);
+    seg[k].count = count;
+    // real items, then (last segment of a run) empty padding items
+    for (int64_t w = off; w < (int64_t)off + n_items; ++w) {
+      if (w >= item_cap) {
+        atomicOr(&cnt->err, kErrCapacity);
+        break;
+      }
+      const int32_t s = (int32_t)(w - off) * kItem;
+      Item it;
+      it.seg = (int32_t)k;
+      it.start = start + (s < count ? s : 0);
+      it.count = s < count ? min(kItem, count - s) : 0;
+      it.pad = 0;
+      items[w] = it;
+    }
+  }
+};
+
+void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_t *tot,
+                     const int32_t *sbody, const BodyLay *blay, const SceneLay *slay,
+                     Segment *seg, int64_t seg_cap, Item *items, int64_t item_cap, int32_t *smark,
+                     int64_t smap_cap, int32_t *bmark, int64_t bmap_cap, int align, Counters *cnt,
+                     hipStream_t st) {
+  if (n <= 0) return;
+  SegHeadIn hin{keys};
+  SegHeadOut hout{keys, sbody, blay, slay, seg, seg_cap, smark, bmark, smap_cap, bmap_cap, cnt,
+                  tot};
+  APIC_LAUNCH((k_scan_onepass<SegHeadIn, SegHeadOut>), dim3(scan_tiles(n)), dim3(kScanThreads),
+              0, st, hin, hout, n, (const int64_t *)nullptr, &tot[0], lb.flags, lb.state);
+  SegItemsIn iin{seg, n, align};
+  ItemsOut iout{seg, n, items, item_cap, cnt};
+  APIC_LAUNCH((k_scan_onepass<SegItemsIn, ItemsOut>), dim3(scan_tiles(seg_cap)),
+              dim3(kScanThreads), 0, st, iin, iout, seg_cap, (const int64_t *)&tot[0], &tot[1],
+              lb.flags, lb.state);
+}
+
+// ---------------------------------------------------------------------------
+// node-block maps
+// ---------------------------------------------------------------------------
 // Each segment's 8 slots; the marks are cleared for the next step, and the
 // first thread turns the slot totals into block counts (with capacity checks).
 __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const SceneLay *slay,
                             const BodyLay *blay, int32_t *smark, const int32_t *smap,
                             int64_t smap_cap, int32_t *bmark, const int32_t *bmap,
                             int64_t bmap_cap, const int64_t *tot, int64_t sblk_cap,
-                            int64_t bblk_cap) {
-  int64_t ns = cnt->n_seg;
+                            int64_t bblk_cap, int64_t item_cap) {
+  int64_t ns = tot[0];
   if (ns > seg_cap) ns = seg_cap;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
        q += (int64_t)gridDim.x * blockDim.x) {
@@ -780,22 +734,23 @@ __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const 
     if (err) atomicOr(&cnt->err, err);
     cnt->n_sblocks = (int32_t)(s < sblk_cap ? s : sblk_cap);
     cnt->n_bblocks = (int32_t)(b < bblk_cap ? b : bblk_cap);
+    cnt->n_seg = (int32_t)ns;
+    const int64_t w = tot[1];
+    cnt->n_items = (int32_t)(w < item_cap ? w : item_cap);
   }
 }
 
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
-                 int64_t sblk_cap, int64_t bblk_cap, hipStream_t st) {
+                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, hipStream_t st) {
   unsigned g = (unsigned)((seg_cap * 8 + 255) / 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  APIC_LAUNCH(k_mark, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smark, smap_cap,
-              bmark, bmap_cap, tot);
   scan_exclusive(smark, smap, smap_cap, &tot[5], &tot[2], lb, 1, st);
   scan_exclusive(bmark, bmap, bmap_cap, &tot[6], &tot[3], lb, 1, st);
   APIC_LAUNCH(k_seg_slots, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smark, smap,
-              smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap);
+              smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap, item_cap);
 }
 
 // Block-wide reduction of 256 records: one set of atomics per block when all
@@ -847,9 +802,9 @@ template void launch_cells<float>(const float *, const uint16_t *, int64_t, cons
 template void launch_cells<double>(const double *, const uint16_t *, int64_t, const SceneDev *,
                                    int, BodyAcc *, BoxRec *, Counters *, hipStream_t);
 template void launch_keys<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
-                                 const BodyLay *, uint32_t *, hipStream_t);
+                                 const BodyLay *, uint32_t *, int, uint32_t *, hipStream_t);
 template void launch_keys<double>(const double *, const uint16_t *, int64_t, const SceneDev *, int,
-                                  const BodyLay *, uint32_t *, hipStream_t);
+                                 const BodyLay *, uint32_t *, int, uint32_t *, hipStream_t);
 template void launch_gather<float>(const uint32_t *, const uint32_t *, int64_t, const float *,
     const float *, const float *, const float *, const uint16_t *, const SceneDev *, int, float *,
     float *, float *, int32_t *, float *, uint16_t *, const uint32_t *, uint32_t *, uint32_t *,

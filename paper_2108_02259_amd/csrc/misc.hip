@@ -4,12 +4,6 @@
 
 namespace apic {
 
-__global__ void k_copy_sticky(Counters *cnt, const int32_t *sticky) { cnt->err = *sticky; }
-
-void launch_copy_sticky(Counters *cnt, const int32_t *sticky, hipStream_t st) {
-  APIC_LAUNCH(k_copy_sticky, dim3(1), dim3(1), 0, st, cnt, sticky);
-}
-
 __global__ void k_clear_sticky(SimDev *dev) { dev->sticky = 0; }
 
 void launch_clear_sticky(SimDev *dev, hipStream_t st) { APIC_LAUNCH(k_clear_sticky, dim3(1), dim3(1), 0, st, dev); }

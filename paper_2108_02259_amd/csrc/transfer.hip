@@ -791,8 +791,8 @@ __global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass
 // answer is Vhat = Vbar + D_N.  Round 1 starts from D_0 = H Vbar - Vbar.
 // Y is laid out by particle ([n][12], sorted order): one row per lane.
 // Scenes with n_iter == k-1 finish in round k: they write Vhat and scatter
-// nothing.  FINAL rounds only finish.
-template <typename T, bool FIRST, bool FINAL, int G>
+// nothing.  Round max n_iter + 1 only finishes (k_final).
+template <typename T, bool FIRST, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
 void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *nrm, T *Y,
             GridPtrs g, const uint32_t *perm, T *v_out, T *C_out) {
@@ -804,7 +804,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
   const int64_t n = a.n;
   const T *gcur = (const T *)g.buf[(k - 1) % 3];
   T *gnext = (T *)g.buf[k % 3];
-  if (!FINAL) {  // the buffer round k+1 scatters into (last read by round k-1)
+  {  // the buffer round k+1 scatters into (last read by round k-1)
     T *gclear = (T *)g.buf[(k + 1) % 3];
     const int64_t words = (int64_t)a.cnt->n_sblocks * 3 * kNodesPerBlock;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < words;
@@ -820,7 +820,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
     const Segment &sg = a.seg[it.seg];
     const SceneDev &sd = a.sc[sg.scene];
     if (sd.n_iter < k - 1) continue;  // scene already finished (uniform per group)
-    const bool finishing = FINAL || sd.n_iter == k - 1;
+    const bool finishing = sd.n_iter == k - 1;
     if (member) load_vel_tile<T>(tile[wave], gcur, g.invm, sg.sslot);
     wave_sync();
     const bool active = member && lane < it.count;
@@ -857,7 +857,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 9; ++c)
             C_out[c * n + dst] = lane_ld(vbi + (3 + c) * n, li) + (yr[3 + c] + hC[c]);
         }
-      } else if (!FINAL) {
+      } else {
         T D[12];
         if (FIRST) {
 #pragma unroll
@@ -893,7 +893,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
         lane_st12(Y + 12 * i0, li, yr);
       }
     }
-    if (!FINAL && !finishing) {
+    if (!finishing) {
       // every lane has gathered: reuse the tile as the scatter target
       int passes = 0;
       const int rank = cell_rank(active, key & 63u, &passes);
@@ -909,6 +909,106 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       }
       flush_group<T, G, 3>(a, tile, gl, member, it.seg, gnext, 3);
     }
+    wave_sync();
+  }
+}
+
+
+// The last round (k = max n_iter + 1): G2P of the last field for the scenes
+// finishing now, Vhat to (v_out, C_out) at perm[i] (or i), then for every
+// particle -- including those of scenes that finished in earlier rounds,
+// whose Vhat is read back -- the FP64 momentum after the step (positions
+// before the drift, the stored T values of Vhat), the resident driver's
+// drift x += dt v when `drift` is set, and one per-scene record per work item
+// (a work item is one scene; padding items write key -1).
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, const T *m,
+                                              const T *vbar, const T *nrm, const T *Y, GridPtrs g,
+                                              const uint32_t *perm, T *v_out, T *C_out, T *x,
+                                              int drift, RedRec *rec) {
+  __shared__ T tile[1][3][kTileSize];
+  const uint32_t lane = threadIdx.x;
+  const int64_t n = a.n;
+  const T *gcur = (const T *)g.buf[(k - 1) % 3];
+  for (ItemLoop L = item_loop(a); L.w < L.end; L.w += L.step) {
+    const int w = L.w;
+    const Item it = a.items[w];
+    if (it.count == 0) {  // run padding
+      if (lane == 0) rec[w].key = -1;
+      continue;
+    }
+    const Segment &sg = a.seg[it.seg];
+    const int s = sg.scene;
+    const SceneDev &sd = a.sc[s];
+    const bool now = sd.n_iter == k - 1;  // wave-uniform
+    if (now) load_vel_tile<T>(tile[0], gcur, g.invm, sg.sslot);
+    wave_sync();
+    const bool active = (int)lane < it.count;
+    const uint32_t li = active ? lane : 0u;
+    const int64_t i0 = it.start;
+    double q[kRed];
+#pragma unroll
+    for (int c = 0; c < kRed; ++c) q[c] = 0.0;
+    if (active) {
+      const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
+      T out[12];
+      if (now) {
+        const T h = (T)sd.h;
+        T tt[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
+        Stencil<T> S;
+        make_stencil(tt, h, S);
+        T hv[3], hC[9];
+        g2p(tile[0], particle_base(lane_ld(a.keys + i0, li)), S, T(2) / (h * h), hv, hC);
+        if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[c] = hv[c];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) out[3 + c] = hC[c];
+        } else {
+          T yr[12];
+          lane_ld12(Y + 12 * i0, li, yr);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[c] = lane_ld(vbar + c * n + i0, li) + (yr[c] + hv[c]);
+#pragma unroll
+          for (int c = 0; c < 9; ++c)
+            out[3 + c] = lane_ld(vbar + (3 + c) * n + i0, li) + (yr[3 + c] + hC[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v_out[c * n + dst] = out[c];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) C_out[c * n + dst] = out[3 + c];
+      } else {  // finished in an earlier round
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = v_out[c * n + dst];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) out[3 + c] = C_out[c * n + dst];
+      }
+      double r[3], vv[3], CC[9];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        vv[d] = (double)out[d];
+        r[d] = (double)x[d * n + dst] - sd.origin[d];
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) CC[c] = (double)out[3 + c];
+      momentum_terms(r, vv, CC, (double)lane_ld(m + i0, li), sd.h, q);
+      if (sd.n_iter > 0) {
+        const T *ni = nrm + i0;
+        q[10] = (lane_ld(ni, li) == T(0) && lane_ld(ni + n, li) == T(0) &&
+                 lane_ld(ni + 2 * n, li) == T(0)) ? 1.0 : 0.0;
+      }
+      if (drift)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d * n + dst] = x[d * n + dst] + (T)(sd.dt * vv[d]);
+    }
+#pragma unroll
+    for (int c = 0; c < kRed; ++c) {
+      const double v = wave_sum(q[c]);
+      if (lane == 0) rec[w].v[c] = v;
+    }
+    if (lane == 0) rec[w].key = s;
     wave_sync();
   }
 }
@@ -951,22 +1051,11 @@ void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st) {
 }
 
 template <typename T>
-void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, const T *vbar,
-                 const T *nrm, T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out,
-                 hipStream_t st) {
-  // finishing-only rounds scatter nothing: one wave per item
-  if (final) {
-    if (k == 1)
-      APIC_LAUNCH((k_iter<T, true, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m, vbar,
-                  nrm, Y, g, perm, v_out, C_out);
-    else
-      APIC_LAUNCH((k_iter<T, false, true, 1>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m,
-                  vbar, nrm, Y, g, perm, v_out, C_out);
-    return;
-  }
+void launch_round(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
+                  T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, hipStream_t st) {
 #define L_ITER(FIRST_) \
-  APIC_LAUNCH((k_iter<T, FIRST_, false, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
-              vbar, nrm, Y, g, perm, v_out, C_out)
+  APIC_LAUNCH((k_iter<T, FIRST_, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, vbar, \
+              nrm, Y, g, perm, v_out, C_out)
   if (k == 1)
     APIC_GROUP_DISPATCH(L_ITER, true);
   else
@@ -974,14 +1063,29 @@ void launch_iter(const StepArgs &a, int k, bool final, const T *t, const T *m, c
 #undef L_ITER
 }
 
+template <typename T>
+void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
+                  const T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, T *x,
+                  int drift, RedRec *rec, hipStream_t st) {
+  if (k == 1)
+    APIC_LAUNCH((k_final<T, true>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y,
+                g, perm, v_out, C_out, x, drift, rec);
+  else
+    APIC_LAUNCH((k_final<T, false>), dim3(a.item_wg), dim3(64), 0, st, a, k, t, m, vbar, nrm, Y,
+                g, perm, v_out, C_out, x, drift, rec);
+}
+
 #define INST(T)                                                                                 \
   template void launch_mass<T>(const StepArgs &, const T *, const T *, GridPtrs, hipStream_t);  \
   template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, T *,         \
                                GridPtrs, hipStream_t);                                          \
   template void launch_grid_clear<T>(const StepArgs &, GridPtrs, hipStream_t);                 \
-  template void launch_iter<T>(const StepArgs &, int, bool, const T *, const T *, const T *,     \
-                               const T *, T *, GridPtrs, const uint32_t *, T *, T *,            \
-                               hipStream_t);
+  template void launch_round<T>(const StepArgs &, int, const T *, const T *, const T *,          \
+                                const T *, T *, GridPtrs, const uint32_t *, T *, T *,           \
+                                hipStream_t);                                                   \
+  template void launch_final<T>(const StepArgs &, int, const T *, const T *, const T *,          \
+                                const T *, const T *, GridPtrs, const uint32_t *, T *, T *, T *, \
+                                int, RedRec *, hipStream_t);
 INST(float)
 INST(double)
 #undef INST
