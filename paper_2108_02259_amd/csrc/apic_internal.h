@@ -33,7 +33,12 @@ constexpr int kNodesPerBlock = 64;
 constexpr int kTileX = 8;               // tile row length
 constexpr int kTileY = 8;               // rows per slab
 constexpr int kTileZStride = 8 * 8 + 4; // padded slab stride (LDS banks)
-constexpr int kTileSize = 8 * kTileZStride;  // elements per component
+// Elements per component of a tile: the 8 * kTileZStride = 544 used, padded
+// to 576 = 9 * 64 so that the components lie a multiple of 256 bytes apart
+// and one LDS instruction can address two of them (the read2st64 /
+// write2st64 forms).
+constexpr int kTileSize = 576;
+static_assert(kTileSize >= 8 * kTileZStride, "tile");
 constexpr int kItem = 64;                // particles per work item (one wave)
 constexpr int kMaxKeyBlocks = 1 << 26;   // 26 block bits + 6 cell bits = 32
 
