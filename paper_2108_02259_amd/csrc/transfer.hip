@@ -25,7 +25,7 @@
 
 // Occupancy targets (waves per SIMD) handed to the register allocator; the
 // FP64 kernels need twice the registers for the same state.
-#define APIC_ROUND_WAVES (sizeof(T) == 4 ? 4 : 2)
+#define APIC_ROUND_WAVES (sizeof(T) == 4 ? 5 : 2)
 #define APIC_P2G_WAVES (sizeof(T) == 4 ? 5 : 3)
 
 namespace apic {
@@ -72,6 +72,15 @@ __device__ __forceinline__ void lane_st(double *p, uint32_t li, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), lane_rsrc(p), li * 8u, 0, 0);
 }
 
+// Lane index formed afresh at the point of use: lane-dependent offsets
+// derived from it are recomputed where needed (a few integer operations)
+// instead of being hoisted out of the item loop and held in registers.
+__device__ __forceinline__ int fresh_lane() {
+  int l = (int)(threadIdx.x & 63);
+  pin(l);
+  return l;
+}
+
 // The 12 values of one particle's row in a [n][12] array (row pointer p
 // wave-uniform, lane li reads row li), in 16-byte loads / stores.
 template <typename T>
@@ -80,7 +89,7 @@ __device__ __forceinline__ void lane_ld12(const T *p, uint32_t li, T v[12]) {
   const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
 #pragma unroll
   for (int k = 0; k < 12 / kPer; ++k) {
-    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow + 16 * k, 0, 0);
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow, 16 * k, 0);
     T e[kPer];
     __builtin_memcpy(e, &q, 16);
 #pragma unroll
@@ -98,7 +107,7 @@ __device__ __forceinline__ void lane_st12(T *p, uint32_t li, const T v[12]) {
     for (int x = 0; x < kPer; ++x) e[x] = v[k * kPer + x];
     decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
     __builtin_memcpy(&q, e, 16);
-    __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow + 16 * k, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow, 16 * k, 0);
   }
 }
 
@@ -189,7 +198,11 @@ __device__ __forceinline__ void g2p(const T (*tv)[kTileSize], int base, const St
 template <typename T>
 __device__ __forceinline__ void p2g(T (*tq)[kTileSize], int base, const Stencil<T> &S, T m,
                                     const T u[3], const T E[9]) {
+  // Pinned at entry: what is derived from the inputs is formed here, row by
+  // row, not hoisted out of the caller's pass loop (which would keep every
+  // row's operands live at once).
   T mu[3], mE[3][3];
+  pin(m);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     mu[q] = m * u[q];
@@ -234,6 +247,7 @@ __device__ __forceinline__ void p2g(T (*tq)[kTileSize], int base, const Stencil<
 // race-freedom argument as p2g.
 template <typename T>
 __device__ __forceinline__ void p2g_mass(T *tm, int base, const Stencil<T> &S, T m) {
+  pin(m);  // as in p2g
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -347,7 +361,7 @@ __device__ __forceinline__ void undesirable(const double d[3], const double n[3]
 template <typename T, int NC>
 __device__ __forceinline__ void load_tile(T (*tile)[kTileSize], const T *buf, const int32_t *slot,
                                           int comps_in_buf) {
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = (uint32_t)fresh_lane();
   int s[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) s[j] = __builtin_amdgcn_readfirstlane(slot[j]);
@@ -375,7 +389,7 @@ __device__ __forceinline__ void load_tile(T (*tile)[kTileSize], const T *buf, co
 template <typename T>
 __device__ __forceinline__ void load_vel_tile(T (*tile)[kTileSize], const T *q, const double *invm,
                                               const int32_t *slot) {
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = (uint32_t)fresh_lane();
   int s[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) s[j] = __builtin_amdgcn_readfirstlane(slot[j]);
@@ -416,7 +430,7 @@ __device__ __forceinline__ void flush_tile(T (*tile)[kTileSize], T *buf, const i
 
 template <typename T, int NC>
 __device__ __forceinline__ void zero_tile(T (*tile)[kTileSize]) {
-  const int lane = threadIdx.x & 63;
+  const int lane = fresh_lane();
   for (int i = lane; i < kTileSize; i += 64)
 #pragma unroll
     for (int q = 0; q < NC; ++q) tile[q][i] = T(0);
@@ -519,7 +533,7 @@ __device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl)
 template <typename T, int G, int NC>
 __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const GroupLds<G> &gl,
                                             T *buf, int comps_in_buf) {
-  const int lane = threadIdx.x & 63;
+  const int lane = fresh_lane();
   const int loff = tile_index_block(0, lane);
   for (int J = wave_id(); J < 27; J += G) {
     const uint32_t mask = __builtin_amdgcn_readfirstlane(gl.mask[J]);
