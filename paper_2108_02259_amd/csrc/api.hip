@@ -207,7 +207,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.sort_bits = bits;
   P.smap_cap = std::max<int64_t>(1, (int64_t)std::ceil(smap_total * headroom));
   P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
-  P.seg_cap = std::max<int64_t>(n, 1);
+  // segments are distinct (body, block) keys present
+  P.seg_cap = std::max<int64_t>(1, std::min<int64_t>(n, kb));
   // items: one per segment plus one per 64 particles, plus the run padding
   // (fewer than the group size per run, one run per super block of a body,
   // and a body's super blocks number 8 block keys each); segments are
@@ -240,8 +241,9 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kKeysB, sizeof(uint32_t) * n));
   TRY(W.ensure(kValsB, sizeof(uint32_t) * n));
   TRY(W.ensure(kGhist, sizeof(uint32_t) * radix_hist_words(n)));
-  const int64_t lbcap = scan_tile_count(
-      std::max<int64_t>({n, P.seg_cap, P.smap_cap, P.bmap_cap, 256 * ntiles}));
+  const int64_t lbcap = std::max<int64_t>(
+      scan_tile_count(std::max<int64_t>({n, P.smap_cap, P.bmap_cap, 256 * ntiles})),
+      scan_tile_count(P.seg_cap, 1));
   TRY(W.ensure(kLbFlags, sizeof(uint64_t) * lbcap));
   TRY(W.ensure(kLbState, sizeof(uint32_t) * 2));
   TRY(W.ensure(kT, T * 3 * n));
@@ -746,13 +748,14 @@ int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec
   const int64_t tb = prec == APIC_FP64 ? 8 : 4;
   if (blocks_hint <= 0) blocks_hint = n / 16 + 64;
   // resident state x2 (x, vC, m, body, orig), sorted scratch (t, m, normals,
-  // series), keys/values x2, segment table; work items and their reduction
-  // records (one per 64 particles plus about two per block); grid mass, 3
-  // momentum buffers, 1/m and per-body mass per node block.
+  // series), keys/values x2; work items and their reduction records (one per
+  // 64 particles plus about two per block), one segment per block; grid mass,
+  // 3 momentum buffers, 1/m and per-body mass per node block.
   const int64_t per_item = (int64_t)(sizeof(Item) + sizeof(RedRec));
   int64_t per_particle = 2 * (tb * 16 + 2 + 4) + tb * (3 + 1 + 3 + 12) + 4 * 5 + 16 +
-                         (int64_t)sizeof(Segment) + per_item / kItem + 1;
-  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2 + 2 * per_item;
+                         per_item / kItem + 1;
+  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2 + 2 * per_item +
+                      (int64_t)sizeof(Segment);
   return n * per_particle + blocks_hint * per_block + (1 << 20);
 }
 

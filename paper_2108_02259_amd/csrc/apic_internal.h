@@ -98,8 +98,9 @@ struct BodyLay {
   int32_t scene;
 };
 
-// One segment = the particles of one (body, cell block).
-struct Segment {
+// One segment = the particles of one (body, cell block).  16-byte aligned
+// (96 bytes) so that it moves in 16-byte loads and stores.
+struct alignas(16) Segment {
   int32_t start, count;
   int32_t body;          // capacity body index
   int32_t scene;

@@ -10,8 +10,9 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-inline int64_t scan_tile_count(int64_t n_cap) {
-  return (n_cap + kScanTile - 1) / kScanTile + 1;
+inline int64_t scan_tile_count(int64_t n_cap, int items = kScanItems) {
+  const int64_t tile = (int64_t)kScanThreads * items;
+  return (n_cap + tile - 1) / tile + 1;
 }
 
 // Device state of the single-pass scans and sort passes (decoupled

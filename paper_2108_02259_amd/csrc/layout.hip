@@ -544,12 +544,14 @@ void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const 
 
 // The segment tables come from two single-pass scans.  The first runs over
 // the sorted particles: a particle whose block key differs from its
-// predecessor's starts a segment, and the scan's output step writes that
-// segment (start, body, scene, block) at its index and marks the 8 shared and
-// 8 body node blocks it touches.  The second runs over the segments: each
+// predecessor's starts a segment, and the scan's output step stores that
+// segment's start.  The second runs over the segments, one per thread: each
 // contributes its work items (one per 64 particles, plus the run padding on
-// the last segment of a run), and the output step writes its particle count
-// and its items.
+// the last segment of a run), and the output step fills in the segment
+// (count, body, scene, block), marks the 8 shared and 8 body node blocks it
+// touches, and writes its items.  Runs are recognised from the keys: a
+// body's first block key is a multiple of 8, so key >> 9 names the (body,
+// super block) pair.
 
 __device__ __forceinline__ int64_t smap_index(const SceneLay &L, int bx, int by, int bz) {
   int rx = bx - L.smin[0], ry = by - L.smin[1], rz = bz - L.smin[2];
@@ -571,85 +573,47 @@ struct SegHeadIn {
 };
 
 struct SegHeadOut {
-  const uint32_t *keys;
-  const int32_t *sbody;
-  const BodyLay *blay;
-  const SceneLay *slay;
   Segment *seg;
   int64_t seg_cap;
-  int32_t *smark, *bmark;
-  int64_t smap_cap, bmap_cap;
   Counters *cnt;
-  int64_t *tot;
-  __device__ void operator()(int64_t i, int head, int k, int64_t) const {
-    if (i == 0) {  // slot-map extents for the map scans
-      tot[5] = cnt->smap_total;
-      tot[6] = cnt->bmap_total;
-    }
+  __device__ __forceinline__ void operator()(int64_t i, int head, int k, int64_t) const {
     if (!head) return;
-    if (k >= seg_cap) {
+    if (k >= seg_cap)
       atomicOr(&cnt->err, kErrCapacity);
-      return;
-    }
-    const uint32_t key = keys[i];
-    const int gb = sbody[i];
-    const BodyLay bl = blay[gb];
-    const int64_t local = (int64_t)(key >> 6) - bl.key_off;
-    const int sub = (int)(local & 7);
-    const int64_t sl = local >> 3;
-    const int ex = bl.kext[0] > 0 ? bl.kext[0] : 1, ey = bl.kext[1] > 0 ? bl.kext[1] : 1;
-    Segment sg;
-    sg.start = (int32_t)i;
-    sg.count = 0;
-    sg.body = gb;
-    sg.scene = bl.scene;
-    sg.B[0] = 2 * (bl.kmin[0] + (int)(sl % ex)) + (sub & 1);
-    sg.B[1] = 2 * (bl.kmin[1] + (int)((sl / ex) % ey)) + ((sub >> 1) & 1);
-    sg.B[2] = 2 * (bl.kmin[2] + (int)(sl / ((int64_t)ex * ey))) + ((sub >> 2) & 1);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      sg.sslot[j] = -1;
-      sg.bslot[j] = -1;
-    }
-    seg[k] = sg;
-    const SceneLay sl_ = slay[bl.scene];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int bx = sg.B[0] + (j & 1), by = sg.B[1] + ((j >> 1) & 1), bz = sg.B[2] + (j >> 2);
-      const int64_t si = smap_index(sl_, bx, by, bz);
-      const int64_t bi = bmap_index(bl, bx, by, bz);
-      if (si >= 0 && si < smap_cap) smark[si] = 1;
-      if (bi >= 0 && bi < bmap_cap) bmark[bi] = 1;
-    }
+    else
+      seg[k].start = (int32_t)i;
   }
 };
 
-// Segments of one body whose blocks lie in one 2x2x2 super block (a run: at
-// most 8 consecutive segments, one per block).  Reads the fields the first
-// scan wrote (never count, which the second scan's output step writes).
-__device__ __forceinline__ bool same_run(const Segment *seg, int64_t a, int64_t b) {
-  return seg[a].body == seg[b].body && (seg[a].B[0] >> 1) == (seg[b].B[0] >> 1) &&
-         (seg[a].B[1] >> 1) == (seg[b].B[1] >> 1) && (seg[a].B[2] >> 1) == (seg[b].B[2] >> 1);
-}
-
-__device__ __forceinline__ int64_t seg_end(const Segment *seg, int64_t k, int64_t ns,
-                                           int64_t np) {
-  return (k + 1 < ns) ? seg[k + 1].start : np;
+__device__ __forceinline__ int32_t seg_start(const Segment *seg, int64_t k, int64_t ns,
+                                             int64_t np) {
+  return k < ns ? seg[k].start : (int32_t)np;
 }
 
 // Work items of segment k: one per 64 particles; the last segment of a run
-// also takes the run's padding to a multiple of `align`.
+// also takes the run's padding to a multiple of `align`.  Reads only the
+// starts the first scan wrote.
 struct SegItemsIn {
   const Segment *seg;
+  const uint32_t *keys;
   int64_t np;
   int align;
   __device__ int operator()(int64_t k, int64_t ns) const {
-    int32_t items = (int32_t)((seg_end(seg, k, ns, np) - seg[k].start + kItem - 1) / kItem);
-    if (align > 1 && (k + 1 == ns || !same_run(seg, k + 1, k))) {
-      int32_t run = items;
-      for (int64_t h = k - 1; h >= 0 && k - h < 8 && same_run(seg, h, k); --h)
-        run += (int32_t)((seg_end(seg, h, ns, np) - seg[h].start + kItem - 1) / kItem);
-      items += (align - run % align) % align;
+    const int32_t st = seg[k].start, en = seg_start(seg, k + 1, ns, np);
+    int32_t items = (en - st + kItem - 1) / kItem;
+    if (align > 1) {
+      const uint32_t run = keys[st] >> 9;
+      if (k + 1 == ns || (keys[en] >> 9) != run) {  // last segment of its run
+        int32_t total = items;
+        int32_t hi = st;
+        for (int64_t h = k - 1; h >= 0 && k - h < 8; --h) {
+          const int32_t lo = seg[h].start;
+          if ((keys[lo] >> 9) != run) break;
+          total += (hi - lo + kItem - 1) / kItem;
+          hi = lo;
+        }
+        items += (align - total % align) % align;
+      }
     }
     return items;
   }
@@ -657,14 +621,52 @@ struct SegItemsIn {
 
 struct ItemsOut {
   Segment *seg;
-  int64_t np;
+  const uint32_t *keys;
+  const int32_t *sbody;
+  const BodyLay *blay;
+  const SceneLay *slay;
+  int32_t *smark, *bmark;
+  int64_t smap_cap, bmap_cap;
   Item *items;
   int64_t item_cap;
   Counters *cnt;
+  int64_t *tot;
+  int64_t np;
   __device__ void operator()(int64_t k, int n_items, int off, int64_t ns) const {
-    const int32_t start = seg[k].start;
-    const int32_t count = (int32_t)(seg_end(seg, k, ns, np) - start);
-    seg[k].count = count;
+    if (k == 0) {  // slot-map extents for the map scans
+      tot[5] = cnt->smap_total;
+      tot[6] = cnt->bmap_total;
+    }
+    Segment &sg = seg[k];
+    const int32_t start = sg.start;
+    const int32_t count = seg_start(seg, k + 1, ns, np) - start;
+    const uint32_t key = keys[start];
+    const int gb = sbody[start];
+    const BodyLay bl = blay[gb];
+    const int64_t local = (int64_t)(key >> 6) - bl.key_off;
+    const int sub = (int)(local & 7);
+    const int64_t sl = local >> 3;
+    const int ex = bl.kext[0] > 0 ? bl.kext[0] : 1, ey = bl.kext[1] > 0 ? bl.kext[1] : 1;
+    int32_t B[3];
+    B[0] = 2 * (bl.kmin[0] + (int)(sl % ex)) + (sub & 1);
+    B[1] = 2 * (bl.kmin[1] + (int)((sl / ex) % ey)) + ((sub >> 1) & 1);
+    B[2] = 2 * (bl.kmin[2] + (int)(sl / ((int64_t)ex * ey))) + ((sub >> 2) & 1);
+    sg.count = count;
+    sg.body = gb;
+    sg.scene = bl.scene;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sg.B[d] = B[d];
+    const SceneLay sl_ = slay[bl.scene];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sg.sslot[j] = -1;
+      sg.bslot[j] = -1;
+      const int bx = B[0] + (j & 1), by = B[1] + ((j >> 1) & 1), bz = B[2] + (j >> 2);
+      const int64_t si = smap_index(sl_, bx, by, bz);
+      const int64_t bi = bmap_index(bl, bx, by, bz);
+      if (si >= 0 && si < smap_cap) smark[si] = 1;
+      if (bi >= 0 && bi < bmap_cap) bmark[bi] = 1;
+    }
     // real items, then (last segment of a run) empty padding items
     for (int64_t w = off; w < (int64_t)off + n_items; ++w) {
       if (w >= item_cap) {
@@ -689,13 +691,13 @@ void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_
                      hipStream_t st) {
   if (n <= 0) return;
   SegHeadIn hin{keys};
-  SegHeadOut hout{keys, sbody, blay, slay, seg, seg_cap, smark, bmark, smap_cap, bmap_cap, cnt,
-                  tot};
+  SegHeadOut hout{seg, seg_cap, cnt};
   APIC_LAUNCH((k_scan_onepass<SegHeadIn, SegHeadOut>), dim3(scan_tiles(n)), dim3(kScanThreads),
               0, st, hin, hout, n, (const int64_t *)nullptr, &tot[0], lb.flags, lb.state);
-  SegItemsIn iin{seg, n, align};
-  ItemsOut iout{seg, n, items, item_cap, cnt};
-  APIC_LAUNCH((k_scan_onepass<SegItemsIn, ItemsOut>), dim3(scan_tiles(seg_cap)),
+  SegItemsIn iin{seg, keys, n, align};
+  ItemsOut iout{seg, keys, sbody, blay, slay, smark, bmark, smap_cap, bmap_cap, items, item_cap,
+                cnt, tot, n};
+  APIC_LAUNCH((k_scan_onepass<SegItemsIn, ItemsOut, 1>), dim3(scan_tiles(seg_cap, 1)),
               dim3(kScanThreads), 0, st, iin, iout, seg_cap, (const int64_t *)&tot[0], &tot[1],
               lb.flags, lb.state);
 }

@@ -104,10 +104,11 @@ struct ArrayOut {
   }
 };
 
-template <typename In>
+template <int ITEMS, typename In>
 __device__ uint32_t tile_sum(const In &in, int64_t n, int64_t tile) {
+  constexpr int64_t kTile = (int64_t)kScanThreads * ITEMS;
   uint32_t s = 0;
-  const int64_t lo = tile * kScanTile, hi = lo + kScanTile < n ? lo + kScanTile : n;
+  const int64_t lo = tile * kTile, hi = lo + kTile < n ? lo + kTile : n;
   for (int64_t i = lo; i < hi; ++i) s += (uint32_t)in(i, n);
   return s;
 }
@@ -148,7 +149,10 @@ __device__ uint32_t wave_lookback(const uint64_t *flags, int64_t stride, int t, 
   return excl;
 }
 
-template <typename In, typename Out>
+// ITEMS consecutive elements per thread (kScanItems for long arrays; 1 for
+// short tables whose per-element work is heavy, so that they spread over
+// more workgroups).
+template <typename In, typename Out, int ITEMS = kScanItems>
 __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, int64_t n_cap,
                                                                const int64_t *n_dev,
                                                                int64_t *total, uint64_t *flags,
@@ -158,13 +162,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, i
   const int64_t n = dev_count(n_cap, n_dev);
   const int t = blockIdx.x;
   const uint32_t epoch = lb_epoch(state);
-  const int last = n > 0 ? (int)((n - 1) / kScanTile) : 0;  // last tile holding data
+  constexpr int64_t kTile = (int64_t)kScanThreads * ITEMS;
+  const int last = n > 0 ? (int)((n - 1) / kTile) : 0;  // last tile holding data
   if (t > last) return;  // past the live count: takes no part
-  const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int v[kScanItems];
+  const int64_t base = (int64_t)t * kTile + (int64_t)threadIdx.x * ITEMS;
+  int v[ITEMS];
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const int64_t i = base + k;
     v[k] = i < n ? in(i, n) : 0;
     s += v[k];
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, i
       if (threadIdx.x == 0) lb_store(&flags[0], lb_pack(epoch, kLbIncl, (uint32_t)tot));
     } else {
       if (threadIdx.x == 0) lb_store(&flags[t], lb_pack(epoch, kLbAgg, (uint32_t)tot));
-      excl = wave_lookback(flags, 1, t, epoch, [&](int j) { return tile_sum(in, n, j); });
+      excl = wave_lookback(flags, 1, t, epoch, [&](int j) { return tile_sum<ITEMS>(in, n, j); });
       if (threadIdx.x == 0) lb_store(&flags[t], lb_pack(epoch, kLbIncl, excl + (uint32_t)tot));
     }
     if (threadIdx.x == 0) {
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, i
   __syncthreads();
   int run = (int)s_excl + ex;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const int64_t i = base + k;
     if (i < n) out(i, v[k], run, n);
     run += v[k];
@@ -196,8 +201,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, i
   if (threadIdx.x == 0) lb_finish(state, epoch, last + 1);
 }
 
-inline unsigned scan_tiles(int64_t n_cap) {
-  int64_t ntiles = (n_cap + kScanTile - 1) / kScanTile;
+inline unsigned scan_tiles(int64_t n_cap, int items = kScanItems) {
+  const int64_t tile = (int64_t)kScanThreads * items;
+  int64_t ntiles = (n_cap + tile - 1) / tile;
   return (unsigned)(ntiles < 1 ? 1 : ntiles);
 }
 
