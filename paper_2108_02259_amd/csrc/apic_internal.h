@@ -179,10 +179,35 @@ __device__ __forceinline__ int tile_index_block(int j, int n) {
 
 __device__ __forceinline__ int floor_div4(int c) { return c >> 2; }  // arithmetic shift
 
+// One DPP step on a double: lane i receives the value of the lane that
+// `CTRL` selects (0 where it selects none, or in rows outside ROW_MASK).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK,
+                                                            0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL,
+                                                            ROW_MASK, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes, returned to every lane.  Must be called with every
+// lane of the wave active.  Data-parallel-primitive steps: swaps within
+// quads (lane ^ 1, lane ^ 2) and rotations by 4 and 8 within each row of 16
+// give every lane its row's sum; row broadcasts then carry row 0 into row 1
+// and rows 0-1 into rows 2-3, so lane 63 holds the total, which is read out
+// as a scalar.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124, 0xf>(v);  // row_ror:4
+  v += dpp_f64<0x128, 0xf>(v);  // row_ror:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,

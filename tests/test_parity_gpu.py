@@ -122,6 +122,14 @@ def test_contact_step_parity(ctx, name, build, mu, n_iter, dtype, tol):
     assert drift_P <= (1e-12 if dtype == np.float64 else 1e-5)
     assert drift_L <= (1e-12 if dtype == np.float64 else 1e-5)
     assert rep["n_particles"] == sc.n
+    # the reported momenta are the device's wave reductions of m v over the
+    # step's inputs and outputs; the host sums the same values in FP64
+    m64 = m.astype(np.float64)
+    P_in = (m64 * v.astype(np.float64)).sum(axis=1)
+    P_out = (m64 * vg.astype(np.float64)).sum(axis=1)
+    scale = rep["P_scale"]
+    assert np.abs(np.array(rep["P_before"]) - P_in).max() <= 1e-12 * scale
+    assert np.abs(np.array(rep["P_after"]) - P_out).max() <= 1e-12 * scale
 
 
 def test_dense_grid_two_cubes_fp64(ctx):
