@@ -262,7 +262,7 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kGBuf1, T * 3 * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kGBuf2, T * 3 * kNodesPerBlock * P.sblk_cap));
   TRY(W.ensure(kInvM, sizeof(double) * kNodesPerBlock * P.sblk_cap));
-  TRY(W.ensure(kBMass, sizeof(double) * kNodesPerBlock * P.bblk_cap));
+  TRY(W.ensure(kBMass, T * kNodesPerBlock * P.bblk_cap));
   TRY(W.ensure(kRecGather, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
   TRY(W.ensure(kRecItems, sizeof(RedRec) * P.item_cap));  // one per work item
   P.rec_gather = (RedRec *)W.ptr[kRecGather];
@@ -291,7 +291,7 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   P.g.buf[1] = W.ptr[kGBuf1];
   P.g.buf[2] = W.ptr[kGBuf2];
   P.g.invm = (double *)W.ptr[kInvM];
-  P.g.bmass = (double *)W.ptr[kBMass];
+  P.g.bmass = W.ptr[kBMass];
   // state that kernels keep between launches starts from zero (mark arrays)
   // or a fresh look-back epoch whenever its buffer is new
   if (W.fresh[kLbFlags] || W.fresh[kLbState]) lookback_init(P.lb, st);
@@ -754,7 +754,7 @@ int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec
   const int64_t per_item = (int64_t)(sizeof(Item) + sizeof(RedRec));
   int64_t per_particle = 2 * (tb * 16 + 2 + 4) + tb * (3 + 1 + 3 + 12) + 4 * 5 + 16 +
                          per_item / kItem + 1;
-  int64_t per_block = kNodesPerBlock * (tb * 10 + 16) + 8 * 2 + 2 * per_item +
+  int64_t per_block = kNodesPerBlock * (tb * 11 + 8) + 8 * 2 + 2 * per_item +
                       (int64_t)sizeof(Segment);
   return n * per_particle + blocks_hint * per_block + (1 << 20);
 }

@@ -108,7 +108,7 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
 struct GridPtrs {
   void *mass;        // [sblk][64] T
   void *buf[3];      // [sblk][3][64] T each: grid momenta, rotating over the rounds
-  double *bmass;     // [bblk][64]
+  void *bmass;       // [bblk][64] T: per-body grid mass
   double *invm;      // [sblk][64]: 1 / mass (0 where the mass is 0)
 };
 

@@ -19,8 +19,9 @@
 // final G2P.  Grid velocities q/m are formed as the rounds load their tiles.
 //
 // Precision: T = float for the mixed path (weights, P2G/G2P accumulation,
-// grid momenta), T = double for the plain FP64 path.  Grid velocity q/m,
-// normals, body masses and the friction rule use double in both.
+// grid masses and momenta, body masses), T = double for the plain FP64 path.
+// Grid velocity q/m, the normals' gradient and the friction rule use double
+// in both.
 #include "kernels.h"
 
 // Occupancy targets (waves per SIMD) handed to the register allocator; the
@@ -287,8 +288,9 @@ __device__ __forceinline__ int cell_rank(bool active, uint32_t cell6, int *passe
 
 // Outward normal from the particle's own-body grid mass: n = -grad m^b / |.|;
 // zero when the gradient vanishes (the particle is then unconstrained).
-__device__ __forceinline__ void body_normal(const double *tb, int base, const double t[3],
-                                            double h, double n[3]) {
+template <typename U>
+__device__ __forceinline__ void body_normal(const U *tb, int base, const double t[3], double h,
+                                            double n[3]) {
   double w[3][4], g[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -311,7 +313,7 @@ __device__ __forceinline__ void body_normal(const double *tb, int base, const do
       double s = 0, sz = 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const double mi = tb[base + a + kTileX * b + kTileZStride * c];
+        const double mi = (double)tb[base + a + kTileX * b + kTileZStride * c];
         s += w[2][c] * mi;
         sz += g[2][c] * mi;
       }
@@ -589,15 +591,15 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
   }
 }
 
-// Flush of a group's mass tiles into both the shared grid mass (T, by
-// sslot) and the body grid mass (FP64, by bslot).  An item's contribution to
-// its body's grid equals its contribution to the shared grid, and a group is
-// one body, so one tile per wave serves both; the body sums are formed in
-// FP64.  The tiles read are left zero.
+// Flush of a group's mass tiles into both the shared grid mass (by sslot)
+// and the body grid mass (by bslot).  An item's contribution to its body's
+// grid equals its contribution to the shared grid, and a group is one body,
+// so one tile per wave and one sum per node serve both.  The tiles read are
+// left zero.
 template <typename T, int G>
 __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1][kTileSize],
                                                  GroupLds<G> &gl, bool flushes, int seg_index,
-                                                 T *mass, double *bmass) {
+                                                 T *mass, T *bmass) {
   const int lane = threadIdx.x & 63;
   if (G == 1) {
     wave_sync();
@@ -612,7 +614,7 @@ __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1
         tiles[0][0][li] = T(0);
         if (v != T(0)) {
           if (s >= 0) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], v);
-          if (b >= 0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], (double)v);
+          if (b >= 0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], v);
         }
       }
     }
@@ -635,22 +637,20 @@ __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1
     if (!mask) continue;
     const int Jx = J % 3, Jy = (J / 3) % 3, Jz = J / 9;
     T sum = T(0);
-    double sumd = 0.0;
 #pragma unroll
     for (int w = 0; w < G; ++w) {
       if (!((mask >> w) & 1u)) continue;
       const int sb = __builtin_amdgcn_readfirstlane(gl.sbi[w]);
       const int j = (Jx - (sb & 1)) + 2 * (Jy - ((sb >> 1) & 1)) + 4 * (Jz - (sb >> 2));
       const int li = tile_index_block(j, 0) + loff;
-      const T v = tiles[w][0][li];
+      sum += tiles[w][0][li];
       tiles[w][0][li] = T(0);
-      sum += v;
-      sumd += (double)v;
     }
+    if (sum == T(0)) continue;
     const int s = __builtin_amdgcn_readfirstlane(gl.slot[J]);
     const int b = __builtin_amdgcn_readfirstlane(gl.bslot[J]);
-    if (s >= 0 && sum != T(0)) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], sum);
-    if (b >= 0 && sumd != 0.0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], sumd);
+    if (s >= 0) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], sum);
+    if (b >= 0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], sum);
   }
   __syncthreads();
 }
@@ -693,7 +693,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
         LDS_ORDER();
       }
     }
-    flush_group_mass<T, G>(a, tm, gl, member, it.seg, (T *)g.mass, g.bmass);
+    flush_group_mass<T, G>(a, tm, gl, member, it.seg, (T *)g.mass, (T *)g.bmass);
   }
 }
 
@@ -708,9 +708,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
 template <typename T, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g) {
-  __shared__ __attribute__((aligned(16))) T tq[G][3][kTileSize];
-  static_assert(3 * kTileSize * sizeof(T) >= kTileSize * sizeof(double), "body-mass tile");
-  static_assert((3 * kTileSize * sizeof(T)) % 16 == 0, "tile alignment");
+  __shared__ T tq[G][3][kTileSize];
   __shared__ GroupLds<G> gl;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   zero_tile<T, 3>(tq[wave]);
@@ -733,20 +731,18 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs 
 #pragma unroll
     for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
     if (member && sd.n_iter > 0) {  // wave-uniform
-      double(*tb)[kTileSize] = reinterpret_cast<double(*)[kTileSize]>(&tq[wave][0][0]);
-      load_tile<double, 1>(tb, g.bmass, sg.bslot, 1);
+      // the body-mass tile in the first component of this wave's P2G tile
+      load_tile<T, 1>(tq[wave], (const T *)g.bmass, sg.bslot, 1);
       wave_sync();
       if (active) {
         const double td[3] = {(double)tt[0], (double)tt[1], (double)tt[2]};
         double nd[3];
-        body_normal(&tb[0][0], base, td, sd.h, nd);
+        body_normal(&tq[wave][0][0], base, td, sd.h, nd);
 #pragma unroll
         for (int c = 0; c < 3; ++c) lane_st(nrm + c * n + i0, li, (T)nd[c]);
       }
       wave_sync();
-      uint4 *z = reinterpret_cast<uint4 *>(&tb[0][0]);
-      for (int k = lane; k < kTileSize * (int)sizeof(double) / 16; k += 64)
-        z[k] = make_uint4(0u, 0u, 0u, 0u);
+      zero_tile<T, 1>(tq[wave]);
       wave_sync();
     }
     int passes;
@@ -783,7 +779,7 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass, T *q0, T *q1,
-                                                    double *bmass) {
+                                                    T *bmass) {
   const int64_t sn = (int64_t)cnt->n_sblocks * kNodesPerBlock;
   const int64_t bn = (int64_t)cnt->n_bblocks * kNodesPerBlock;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -791,10 +787,10 @@ __global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass
     q0[q] = T(0);
     q1[q] = T(0);
     if (q < sn) mass[q] = T(0);
-    if (q < bn) bmass[q] = 0.0;
+    if (q < bn) bmass[q] = T(0);
   }
   for (int64_t q = 3 * sn + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn; q += stride)
-    bmass[q] = 0.0;
+    bmass[q] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1061,7 +1057,7 @@ void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nr
 template <typename T>
 void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st) {
   APIC_LAUNCH((k_grid_clear<T>), dim3(a.node_wg), dim3(256), 0, st, a.cnt, (T *)g.mass,
-              (T *)g.buf[0], (T *)g.buf[1], g.bmass);
+              (T *)g.buf[0], (T *)g.buf[1], (T *)g.bmass);
 }
 
 template <typename T>
