@@ -361,7 +361,8 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   launch_segments(P.keys, n, P.lb, P.tot, P.sbody, P.blay, P.slay, P.seg, P.seg_cap, P.items,
                   P.item_cap, P.smark, P.smap_cap, P.bmark, P.bmap_cap, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
-              P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, P.item_cap, st);
+              P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, P.item_cap, P.g,
+              (int)P.tbytes, P.node_wg, st);
   StepArgs a;
   a.sc = P.sc;
   a.seg = P.seg;
@@ -374,13 +375,12 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.xcd_split = P.xcd_split;
   a.item_wg = P.item_wg;
   a.group = P.group;
-  launch_grid_clear<T>(a, P.g, st);
   if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
   launch_mass<T>(a, t, m_sorted, P.g, st);
   if (prof) prof->end(APIC_KC_MASS, st), prof->begin(st);
-  launch_p2g0<T>(a, t, m_sorted, vbar, nrm, P.g, st);
+  launch_p2g0<T>(a, t, m_sorted, vbar, nrm, P.items, P.g, st);
   if (prof) prof->end(APIC_KC_P2G0, st);
   const uint32_t *perm_out = unpermute ? P.perm : nullptr;
   for (int k = 1; k <= P.max_iter; ++k) {

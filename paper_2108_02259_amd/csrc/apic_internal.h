@@ -114,7 +114,8 @@ struct alignas(16) Segment {
 // (count 0) to a multiple of the step's group size, so that aligned groups
 // of 1, 4 or 8 items never straddle two runs.
 struct Item {
-  int32_t seg, start, count, pad;
+  int32_t seg, start, count;
+  int32_t full_y;  // 1 if one of its particles has no contact normal (set with the normals)
 };
 
 // Counters written by the device, read back by the host when it sizes

@@ -57,6 +57,14 @@ inline int64_t radix_hist_words(int64_t n) { return 2 * 256 * sort_tiles(n) + 4;
 int radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, int64_t n, int lo,
                int bits, uint32_t *hist, const Lookback &lb, bool hist0_ready, hipStream_t st);
 
+// Grid arrays of a step (slot-major, see the transfers).
+struct GridPtrs {
+  void *mass;        // [sblk][64] T
+  void *buf[3];      // [sblk][3][64] T each: grid momenta, rotating over the rounds
+  void *bmass;       // [bblk][64] T: per-body grid mass
+  double *invm;      // [sblk][64]: 1 / mass (0 where the mass is 0)
+};
+
 // ---- layout (layout.hip) ---------------------------------------------------
 // One box record per wavefront (rec has ceil(n/256)*4 entries), then reduced.
 template <typename T>
@@ -98,19 +106,16 @@ void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_
                      hipStream_t st);
 // Node-block maps: scan the marks into slots, store each segment's 8 slots
 // and clear the marks again (so that the mark arrays are all zero between
-// steps); publishes the segment, item and active-block counts.
+// steps); publishes the segment, item and active-block counts, and zeroes
+// the grid mass, momentum buffers 0 and 1 and the body mass over the active
+// blocks (tbytes bytes per value).
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
-                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, hipStream_t st);
+                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
+                 int node_wg, hipStream_t st);
 
 // ---- transfers (transfer.hip) ---------------------------------------------
-struct GridPtrs {
-  void *mass;        // [sblk][64] T
-  void *buf[3];      // [sblk][3][64] T each: grid momenta, rotating over the rounds
-  void *bmass;       // [bblk][64] T: per-body grid mass
-  double *invm;      // [sblk][64]: 1 / mass (0 where the mass is 0)
-};
 
 struct StepArgs {
   const SceneDev *sc;
@@ -129,14 +134,12 @@ struct StepArgs {
 template <typename T>
 void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStream_t st);
 // Contact normals (where a scene has series rounds) and P2G of Vbar into
-// buffer 0, in one pass over the items (after launch_mass).
+// buffer 0, in one pass over the items (after launch_mass).  Sets each
+// item's full_y to 1 if one of its particles has no normal (the rounds then
+// keep full series-state rows for it).
 template <typename T>
-void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g,
-                 hipStream_t st);
-// Zero the grid mass, the first two momentum buffers and the body masses of
-// the active blocks (counts on the device).
-template <typename T>
-void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st);
+void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, Item *items,
+                 GridPtrs g, hipStream_t st);
 // One fused round k = 1 .. max n_iter: G2P of the momenta in buffer
 // (k-1) mod 3 (turned into velocities q/m as the tile is loaded), the rule,
 // P2G of the next series field into buffer k mod 3, and clearing of buffer

@@ -678,7 +678,7 @@ struct ItemsOut {
       it.seg = (int32_t)k;
       it.start = start + (s < count ? s : 0);
       it.count = s < count ? min(kItem, count - s) : 0;
-      it.pad = 0;
+      it.full_y = 0;
       items[w] = it;
     }
   }
@@ -707,11 +707,29 @@ void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_
 // ---------------------------------------------------------------------------
 // Each segment's 8 slots; the marks are cleared for the next step, and the
 // first thread turns the slot totals into block counts (with capacity checks).
+// Also clears the step's accumulation targets over the active blocks (grid
+// mass, momentum buffers 0 and 1, body mass; `words` 32-bit words per node
+// value), which the previous step no longer reads.
 __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const SceneLay *slay,
                             const BodyLay *blay, int32_t *smark, const int32_t *smap,
                             int64_t smap_cap, int32_t *bmark, const int32_t *bmap,
                             int64_t bmap_cap, const int64_t *tot, int64_t sblk_cap,
-                            int64_t bblk_cap, int64_t item_cap) {
+                            int64_t bblk_cap, int64_t item_cap, uint32_t *mass, uint32_t *q0,
+                            uint32_t *q1, uint32_t *bmass, int words) {
+  {
+    const int64_t sn = (tot[2] < sblk_cap ? tot[2] : sblk_cap) * kNodesPerBlock * words;
+    const int64_t bn = (tot[3] < bblk_cap ? tot[3] : bblk_cap) * kNodesPerBlock * words;
+    const int64_t top = 3 * sn > bn ? 3 * sn : bn;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < top;
+         q += (int64_t)gridDim.x * blockDim.x) {
+      if (q < 3 * sn) {
+        q0[q] = 0u;
+        q1[q] = 0u;
+      }
+      if (q < sn) mass[q] = 0u;
+      if (q < bn) bmass[q] = 0u;
+    }
+  }
   int64_t ns = tot[0];
   if (ns > seg_cap) ns = seg_cap;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ns * 8;
@@ -745,14 +763,16 @@ __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const 
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
-                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, hipStream_t st) {
-  unsigned g = (unsigned)((seg_cap * 8 + 255) / 256);
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
+                 int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
+                 int node_wg, hipStream_t st) {
+  int64_t blocks = std::max<int64_t>((seg_cap * 8 + 255) / 256, node_wg);
+  if (blocks > 8192) blocks = 8192;
   scan_exclusive(smark, smap, smap_cap, &tot[5], &tot[2], lb, 1, st);
   scan_exclusive(bmark, bmap, bmap_cap, &tot[6], &tot[3], lb, 1, st);
-  APIC_LAUNCH(k_seg_slots, dim3(g), dim3(256), 0, st, seg, cnt, seg_cap, slay, blay, smark, smap,
-              smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap, item_cap);
+  APIC_LAUNCH(k_seg_slots, dim3((unsigned)blocks), dim3(256), 0, st, seg, cnt, seg_cap, slay,
+              blay, smark, smap, smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap,
+              item_cap, (uint32_t *)g.mass, (uint32_t *)g.buf[0], (uint32_t *)g.buf[1],
+              (uint32_t *)g.bmass, tbytes / 4);
 }
 
 // Block-wide reduction of 256 records: one set of atomics per block when all

@@ -82,33 +82,44 @@ __device__ __forceinline__ int fresh_lane() {
   return l;
 }
 
-// The 12 values of one particle's row in a [n][12] array (row pointer p
-// wave-uniform, lane li reads row li), in 16-byte loads / stores.
+// The series state Y of a particle ([n][12] rows).  For a particle with a
+// contact normal the rule's W takes all of D's affine part, so Y's affine
+// values (3..11) are exactly zero.  `full` is decided per work item (the
+// same particles in every round of a step; Item::full_y, set where the normals
+// are computed): an item none of whose particles lacks a normal moves only
+// the 16-byte chunks holding values 0..3.
 template <typename T>
-__device__ __forceinline__ void lane_ld12(const T *p, uint32_t li, T v[12]) {
-  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T);
+__device__ __forceinline__ void load_y(const T *p, uint32_t li, bool full, T v[12]) {
+  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T), kHead = (4 + kPer - 1) / kPer;
   const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
 #pragma unroll
   for (int k = 0; k < 12 / kPer; ++k) {
-    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow, 16 * k, 0);
     T e[kPer];
-    __builtin_memcpy(e, &q, 16);
+    if (k < kHead || full) {
+      const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow, 16 * k, 0);
+      __builtin_memcpy(e, &q, 16);
+    } else {
+#pragma unroll
+      for (int x = 0; x < kPer; ++x) e[x] = T(0);
+    }
 #pragma unroll
     for (int x = 0; x < kPer; ++x) v[k * kPer + x] = e[x];
   }
 }
 template <typename T>
-__device__ __forceinline__ void lane_st12(T *p, uint32_t li, const T v[12]) {
-  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T);
+__device__ __forceinline__ void store_y(T *p, uint32_t li, bool full, const T v[12]) {
+  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T), kHead = (4 + kPer - 1) / kPer;
   const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
 #pragma unroll
   for (int k = 0; k < 12 / kPer; ++k) {
-    T e[kPer];
+    if (k < kHead || full) {
+      T e[kPer];
 #pragma unroll
-    for (int x = 0; x < kPer; ++x) e[x] = v[k * kPer + x];
-    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
-    __builtin_memcpy(&q, e, 16);
-    __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow, 16 * k, 0);
+      for (int x = 0; x < kPer; ++x) e[x] = v[k * kPer + x];
+      decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
+      __builtin_memcpy(&q, e, 16);
+      __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow, 16 * k, 0);
+    }
   }
 }
 
@@ -707,7 +718,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
 // for scenes without series rounds (unused there).
 template <typename T, int G>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
-void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g) {
+void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *items, GridPtrs g) {
   __shared__ T tq[G][3][kTileSize];
   __shared__ GroupLds<G> gl;
   const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -734,13 +745,22 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs 
       // the body-mass tile in the first component of this wave's P2G tile
       load_tile<T, 1>(tq[wave], (const T *)g.bmass, sg.bslot, 1);
       wave_sync();
+      bool no_nrm = false;
       if (active) {
         const double td[3] = {(double)tt[0], (double)tt[1], (double)tt[2]};
         double nd[3];
         body_normal(&tq[wave][0][0], base, td, sd.h, nd);
+        T nt[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) lane_st(nrm + c * n + i0, li, (T)nd[c]);
+        for (int c = 0; c < 3; ++c) {
+          nt[c] = (T)nd[c];
+          lane_st(nrm + c * n + i0, li, nt[c]);
+        }
+        no_nrm = nt[0] == T(0) && nt[1] == T(0) && nt[2] == T(0);
       }
+      // the item's flag for the rounds: full Y rows if a particle has no normal
+      const uint64_t any = __ballot(no_nrm);
+      if (lane == 0) items[w0 + wave].full_y = any != 0 ? 1 : 0;
       wave_sync();
       zero_tile<T, 1>(tq[wave]);
       wave_sync();
@@ -772,25 +792,6 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs 
     const double mi = (double)mass[q];
     g.invm[q] = mi > 0.0 ? 1.0 / mi : 0.0;
   }
-}
-
-// ---------------------------------------------------------------------------
-// step-start clear of the accumulation targets
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_grid_clear(const Counters *cnt, T *mass, T *q0, T *q1,
-                                                    T *bmass) {
-  const int64_t sn = (int64_t)cnt->n_sblocks * kNodesPerBlock;
-  const int64_t bn = (int64_t)cnt->n_bblocks * kNodesPerBlock;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * sn; q += stride) {
-    q0[q] = T(0);
-    q1[q] = T(0);
-    if (q < sn) mass[q] = T(0);
-    if (q < bn) bmass[q] = T(0);
-  }
-  for (int64_t q = 3 * sn + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn; q += stride)
-    bmass[q] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,6 +852,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       g2p(tile[wave], base, S, T(2) / (h * h), hv, hC);
       const T *vbi = vbar + i0;
       const T *Yi = Y + 12 * i0;  // Y rows: [n][12]
+      const bool full = it.full_y != 0;  // some particle of the item has no normal
       if (finishing) {
         const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
@@ -860,7 +862,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 9; ++c) C_out[c * n + dst] = hC[c];
         } else {
           T yr[12];
-          lane_ld12(Yi, li, yr);
+          load_y(Yi, li, full, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) v_out[c * n + dst] = lane_ld(vbi + c * n, li) + (yr[c] + hv[c]);
 #pragma unroll
@@ -876,7 +878,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - lane_ld(vbi + (3 + c) * n, li);
         } else {
           T yr[12];
-          lane_ld12(Yi, li, yr);
+          load_y(Yi, li, full, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) D[c] = yr[c] + hv[c];
 #pragma unroll
@@ -900,7 +902,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
         T yr[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) yr[c] = D[c] - W[c];
-        lane_st12(Y + 12 * i0, li, yr);
+        store_y(Y + 12 * i0, li, full, yr);
       }
     }
     if (!finishing) {
@@ -940,6 +942,7 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
   const uint32_t lane = threadIdx.x;
   const int64_t n = a.n;
   const T *gcur = (const T *)g.buf[(k - 1) % 3];
+  const bool direct = perm == nullptr;  // outputs at the sorted index (resident state)
   for (ItemLoop L = item_loop(a); L.w < L.end; L.w += L.step) {
     const int w = L.w;
     const Item it = a.items[w];
@@ -978,17 +981,24 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
           for (int c = 0; c < 9; ++c) out[3 + c] = hC[c];
         } else {
           T yr[12];
-          lane_ld12(Y + 12 * i0, li, yr);
+          load_y(Y + 12 * i0, li, it.full_y != 0, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) out[c] = lane_ld(vbar + c * n + i0, li) + (yr[c] + hv[c]);
 #pragma unroll
           for (int c = 0; c < 9; ++c)
             out[3 + c] = lane_ld(vbar + (3 + c) * n + i0, li) + (yr[3 + c] + hC[c]);
         }
+        if (direct) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v_out[c * n + dst] = out[c];
+          for (int c = 0; c < 3; ++c) lane_st(v_out + c * n + i0, li, out[c]);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) C_out[c * n + dst] = out[3 + c];
+          for (int c = 0; c < 9; ++c) lane_st(C_out + c * n + i0, li, out[3 + c]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v_out[c * n + dst] = out[c];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) C_out[c * n + dst] = out[3 + c];
+        }
       } else {  // finished in an earlier round
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[c] = v_out[c * n + dst];
@@ -996,10 +1006,12 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
         for (int c = 0; c < 9; ++c) out[3 + c] = C_out[c * n + dst];
       }
       double r[3], vv[3], CC[9];
+      T xp[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
+        xp[d] = direct ? lane_ld(x + d * n + i0, li) : x[d * n + dst];
         vv[d] = (double)out[d];
-        r[d] = (double)x[d * n + dst] - sd.origin[d];
+        r[d] = (double)xp[d] - sd.origin[d];
       }
 #pragma unroll
       for (int c = 0; c < 9; ++c) CC[c] = (double)out[3 + c];
@@ -1009,9 +1021,16 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
         q[10] = (lane_ld(ni, li) == T(0) && lane_ld(ni + n, li) == T(0) &&
                  lane_ld(ni + 2 * n, li) == T(0)) ? 1.0 : 0.0;
       }
-      if (drift)
+      if (drift) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) x[d * n + dst] = x[d * n + dst] + (T)(sd.dt * vv[d]);
+        for (int d = 0; d < 3; ++d) {
+          const T xn = xp[d] + (T)(sd.dt * vv[d]);
+          if (direct)
+            lane_st(x + d * n + i0, li, xn);
+          else
+            x[d * n + dst] = xn;
+        }
+      }
     }
 #pragma unroll
     for (int c = 0; c < kRed; ++c) {
@@ -1046,18 +1065,13 @@ void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStrea
 }
 
 template <typename T>
-void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, GridPtrs g,
-                 hipStream_t st) {
+void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, Item *items,
+                 GridPtrs g, hipStream_t st) {
 #define L_P2G0() \
-  APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, nrm, g)
+  APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, nrm, \
+              items, g)
   APIC_GROUP_DISPATCH(L_P2G0);
 #undef L_P2G0
-}
-
-template <typename T>
-void launch_grid_clear(const StepArgs &a, GridPtrs g, hipStream_t st) {
-  APIC_LAUNCH((k_grid_clear<T>), dim3(a.node_wg), dim3(256), 0, st, a.cnt, (T *)g.mass,
-              (T *)g.buf[0], (T *)g.buf[1], (T *)g.bmass);
 }
 
 template <typename T>
@@ -1087,9 +1101,8 @@ void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vba
 
 #define INST(T)                                                                                 \
   template void launch_mass<T>(const StepArgs &, const T *, const T *, GridPtrs, hipStream_t);  \
-  template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, T *,         \
+  template void launch_p2g0<T>(const StepArgs &, const T *, const T *, const T *, T *, Item *, \
                                GridPtrs, hipStream_t);                                          \
-  template void launch_grid_clear<T>(const StepArgs &, GridPtrs, hipStream_t);                 \
   template void launch_round<T>(const StepArgs &, int, const T *, const T *, const T *,          \
                                 const T *, T *, GridPtrs, const uint32_t *, T *, T *,           \
                                 hipStream_t);                                                   \
