@@ -68,7 +68,7 @@ static int size_bucket(int64_t n) {
 
 static apic_tuning default_tuning() {
   apic_tuning t;
-  t.item_waves_per_cu = 16;
+  t.item_waves_per_cu = 32;
   t.node_wg_per_cu = 8;
   t.xcd_split = 0;
   t.p2g_group = 4;
@@ -993,7 +993,7 @@ apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
   double best_ms = 1e300;
   // stage 1: work items merged per workgroup, waves per CU, XCD split
   const int group_opts[] = {1, 4, 8};
-  const int wave_opts[] = {8, 16, 24, 32};
+  const int wave_opts[] = {16, 24, 32, 40, 48};
   for (int grp : group_opts) {
     if (prec == APIC_FP64 && grp > 4) continue;
     for (int xs = 0; xs < 2 && rc == APIC_OK; ++xs)
