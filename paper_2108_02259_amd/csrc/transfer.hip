@@ -82,43 +82,54 @@ __device__ __forceinline__ int fresh_lane() {
   return l;
 }
 
-// The series state Y of a particle ([n][12] rows).  For a particle with a
-// contact normal the rule's W takes all of D's affine part, so Y's affine
-// values (3..11) are exactly zero.  `full` is decided per work item (the
-// same particles in every round of a step; Item::full_y, set where the normals
-// are computed): an item none of whose particles lacks a normal moves only
-// the 16-byte chunks holding values 0..3.
+// The series state Y of a particle, in two row arrays: values 0..3 (the
+// velocity part and the first affine value) in Yv = Y[n][4], values 4..11 in
+// YC = (Y + 4n)[n][8].  For a particle with a contact normal the rule's W
+// takes all of D's affine part, so Y's affine values are exactly zero.
+// `full` is decided per work item (the same particles in every round of a
+// step; Item::full_y, set where the normals are computed): an item none of
+// whose particles lacks a normal reads and writes Yv only.
 template <typename T>
-__device__ __forceinline__ void load_y(const T *p, uint32_t li, bool full, T v[12]) {
-  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T), kHead = (4 + kPer - 1) / kPer;
-  const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
+__device__ __forceinline__ void load_y(const T *Y, int64_t n, int64_t i0, uint32_t li, bool full,
+                                       T v[12]) {
+  constexpr int kPer = 16 / sizeof(T);
+  const __amdgpu_buffer_rsrc_t rv = lane_rsrc(Y + 4 * i0);
 #pragma unroll
-  for (int k = 0; k < 12 / kPer; ++k) {
-    T e[kPer];
-    if (k < kHead || full) {
-      const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, li * kRow, 16 * k, 0);
-      __builtin_memcpy(e, &q, 16);
-    } else {
+  for (int k = 0; k < 4 / kPer; ++k) {
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(rv, li * (4 * sizeof(T)), 16 * k, 0);
+    __builtin_memcpy(&v[k * kPer], &q, 16);
+  }
+  if (full) {
+    const __amdgpu_buffer_rsrc_t rc = lane_rsrc(Y + 4 * n + 8 * i0);
 #pragma unroll
-      for (int x = 0; x < kPer; ++x) e[x] = T(0);
+    for (int k = 0; k < 8 / kPer; ++k) {
+      const auto q = __builtin_amdgcn_raw_buffer_load_b128(rc, li * (8 * sizeof(T)), 16 * k, 0);
+      __builtin_memcpy(&v[4 + k * kPer], &q, 16);
     }
+  } else {
 #pragma unroll
-    for (int x = 0; x < kPer; ++x) v[k * kPer + x] = e[x];
+    for (int c = 4; c < 12; ++c) v[c] = T(0);
   }
 }
 template <typename T>
-__device__ __forceinline__ void store_y(T *p, uint32_t li, bool full, const T v[12]) {
-  constexpr int kRow = 12 * sizeof(T), kPer = 16 / sizeof(T), kHead = (4 + kPer - 1) / kPer;
-  const __amdgpu_buffer_rsrc_t r = lane_rsrc(p);
+__device__ __forceinline__ void store_y(T *Y, int64_t n, int64_t i0, uint32_t li, bool full,
+                                        const T v[12]) {
+  constexpr int kPer = 16 / sizeof(T);
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(lane_rsrc(Y), 0, 0, 0));
+  const __amdgpu_buffer_rsrc_t rv = lane_rsrc(Y + 4 * i0);
 #pragma unroll
-  for (int k = 0; k < 12 / kPer; ++k) {
-    if (k < kHead || full) {
-      T e[kPer];
+  for (int k = 0; k < 4 / kPer; ++k) {
+    V q;
+    __builtin_memcpy(&q, &v[k * kPer], 16);
+    __builtin_amdgcn_raw_buffer_store_b128(q, rv, li * (4 * sizeof(T)), 16 * k, 0);
+  }
+  if (full) {
+    const __amdgpu_buffer_rsrc_t rc = lane_rsrc(Y + 4 * n + 8 * i0);
 #pragma unroll
-      for (int x = 0; x < kPer; ++x) e[x] = v[k * kPer + x];
-      decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
-      __builtin_memcpy(&q, e, 16);
-      __builtin_amdgcn_raw_buffer_store_b128(q, r, li * kRow, 16 * k, 0);
+    for (int k = 0; k < 8 / kPer; ++k) {
+      V q;
+      __builtin_memcpy(&q, &v[4 + k * kPer], 16);
+      __builtin_amdgcn_raw_buffer_store_b128(q, rc, li * (8 * sizeof(T)), 16 * k, 0);
     }
   }
 }
@@ -591,8 +602,10 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
     const int sgi = flushes ? seg_index : -1;  // wave-uniform
     const int sbi = flushes ? block_in_super(a.seg[seg_index]) : 0;
     if ((threadIdx.x & 63) == 0) {
-      gl.seg[wave] = sgi;
-      gl.sbi[wave] = sbi;
+      int wv = wave;
+      pin(wv);  // its LDS address formed here, not held across the item loop
+      gl.seg[wv] = sgi;
+      gl.sbi[wv] = sbi;
     }
     __syncthreads();
     group_tables<G>(a, gl);
@@ -800,7 +813,7 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
 // Stored per particle between rounds: Y = D_{k-1} - W_k, so that after the
 // next G2P (of W_k) the accumulated change is D_k = Y + H W_k, and the final
 // answer is Vhat = Vbar + D_N.  Round 1 starts from D_0 = H Vbar - Vbar.
-// Y is laid out by particle ([n][12], sorted order): one row per lane.
+// Y is laid out by particle in two row arrays (see load_y).
 // Scenes with n_iter == k-1 finish in round k: they write Vhat and scatter
 // nothing.  Round max n_iter + 1 only finishes (k_final).
 template <typename T, bool FIRST, int G>
@@ -851,7 +864,6 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       T hv[3], hC[9];
       g2p(tile[wave], base, S, T(2) / (h * h), hv, hC);
       const T *vbi = vbar + i0;
-      const T *Yi = Y + 12 * i0;  // Y rows: [n][12]
       const bool full = it.full_y != 0;  // some particle of the item has no normal
       if (finishing) {
         const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
@@ -862,7 +874,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 9; ++c) C_out[c * n + dst] = hC[c];
         } else {
           T yr[12];
-          load_y(Yi, li, full, yr);
+          load_y(Y, n, i0, li, full, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) v_out[c * n + dst] = lane_ld(vbi + c * n, li) + (yr[c] + hv[c]);
 #pragma unroll
@@ -878,7 +890,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - lane_ld(vbi + (3 + c) * n, li);
         } else {
           T yr[12];
-          load_y(Yi, li, full, yr);
+          load_y(Y, n, i0, li, full, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) D[c] = yr[c] + hv[c];
 #pragma unroll
@@ -902,7 +914,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
         T yr[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) yr[c] = D[c] - W[c];
-        store_y(Y + 12 * i0, li, full, yr);
+        store_y(Y, n, i0, li, full, yr);
       }
     }
     if (!finishing) {
@@ -981,7 +993,7 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
           for (int c = 0; c < 9; ++c) out[3 + c] = hC[c];
         } else {
           T yr[12];
-          load_y(Y + 12 * i0, li, it.full_y != 0, yr);
+          load_y(Y, n, i0, li, it.full_y != 0, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) out[c] = lane_ld(vbar + c * n + i0, li) + (yr[c] + hv[c]);
 #pragma unroll
