@@ -356,13 +356,12 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
                    P.red, st);
   P.keys = keys2;
   P.perm = perm2;
-  launch_reduce_red(P.rec_gather, wave_records(n), nullptr, nullptr, P.red, st);
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
   launch_segments(P.keys, n, P.lb, P.tot, P.sbody, P.blay, P.slay, P.seg, P.seg_cap, P.items,
                   P.item_cap, P.smark, P.smap_cap, P.bmark, P.bmap_cap, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
               P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, P.item_cap, P.g,
-              (int)P.tbytes, P.node_wg, st);
+              (int)P.tbytes, P.node_wg, P.rec_gather, wave_records(n), P.red, st);
   StepArgs a;
   a.sc = P.sc;
   a.seg = P.seg;

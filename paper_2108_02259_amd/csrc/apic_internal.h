@@ -234,6 +234,42 @@ __device__ __forceinline__ void momentum_terms(const double r[3], const double v
   q[10] = 0.0;
 }
 
+// Records [base, base + 256) of [0, count) reduced by one 256-thread
+// workgroup into out[key * kRed + c]: one set of atomics when all of them
+// name one scene, per record otherwise.  Every thread of the workgroup must
+// call it (it synchronises the workgroup).
+__device__ __forceinline__ void reduce_rec_block(const RedRec *rec, int64_t base, int64_t count,
+                                                 double *out) {
+  __shared__ double part[kRed][4];
+  __shared__ int32_t key0;
+  const int64_t i = base + threadIdx.x;
+  int key = -1;
+  if (i < count) key = rec[i].key;
+  if (threadIdx.x == 0) key0 = -2;
+  __syncthreads();
+  if (key >= 0) atomicCAS(&key0, -2, key);
+  __syncthreads();
+  const int k0 = key0;
+  const bool uniform = __syncthreads_and(key < 0 || key == k0);
+  if (k0 >= 0) {  // workgroup-uniform
+    if (uniform) {
+      const int wave = threadIdx.x >> 6;
+      for (int c = 0; c < kRed; ++c) {
+        const double v = wave_sum(key >= 0 ? rec[i].v[c] : 0.0);
+        if ((threadIdx.x & 63) == 0) part[c][wave] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < kRed)
+        atomicAdd(&out[(int64_t)k0 * kRed + threadIdx.x],
+                  part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                      part[threadIdx.x][3]);
+    } else if (key >= 0) {
+      for (int c = 0; c < kRed; ++c) atomicAdd(&out[(int64_t)key * kRed + c], rec[i].v[c]);
+    }
+  }
+  __syncthreads();
+}
+
 // Binary search: the scene whose [offset, offset+count) holds particle p.
 __device__ __forceinline__ int scene_of(const SceneDev *sc, int ns, int64_t p) {
   int lo = 0, hi = ns - 1;

@@ -108,12 +108,14 @@ void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_
 // and clear the marks again (so that the mark arrays are all zero between
 // steps); publishes the segment, item and active-block counts, and zeroes
 // the grid mass, momentum buffers 0 and 1 and the body mass over the active
-// blocks (tbytes bytes per value).
+// blocks (tbytes bytes per value); reduces the records grec[0, grec_count)
+// into gred.
 void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const BodyLay *blay,
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
                  int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
-                 int node_wg, hipStream_t st);
+                 int node_wg, const RedRec *grec, int64_t grec_count, double *gred,
+                 hipStream_t st);
 
 // ---- transfers (transfer.hip) ---------------------------------------------
 

@@ -709,13 +709,18 @@ void launch_segments(const uint32_t *keys, int64_t n, const Lookback &lb, int64_
 // first thread turns the slot totals into block counts (with capacity checks).
 // Also clears the step's accumulation targets over the active blocks (grid
 // mass, momentum buffers 0 and 1, body mass; `words` 32-bit words per node
-// value), which the previous step no longer reads.
+// value), which the previous step no longer reads, and reduces the gather's
+// momentum records into gred.
 __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const SceneLay *slay,
                             const BodyLay *blay, int32_t *smark, const int32_t *smap,
                             int64_t smap_cap, int32_t *bmark, const int32_t *bmap,
                             int64_t bmap_cap, const int64_t *tot, int64_t sblk_cap,
                             int64_t bblk_cap, int64_t item_cap, uint32_t *mass, uint32_t *q0,
-                            uint32_t *q1, uint32_t *bmass, int words) {
+                            uint32_t *q1, uint32_t *bmass, int words, const RedRec *grec,
+                            int64_t grec_count, double *gred) {
+  // the gather's per-wave momentum records (workgroup-uniform loop)
+  for (int64_t rb = blockIdx.x; rb * 256 < grec_count; rb += gridDim.x)
+    reduce_rec_block(grec, rb * 256, grec_count, gred);
   {
     const int64_t sn = (tot[2] < sblk_cap ? tot[2] : sblk_cap) * kNodesPerBlock * words;
     const int64_t bn = (tot[3] < bblk_cap ? tot[3] : bblk_cap) * kNodesPerBlock * words;
@@ -764,7 +769,8 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
                  int32_t *smark, int32_t *smap, int64_t smap_cap, int32_t *bmark, int32_t *bmap,
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
                  int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
-                 int node_wg, hipStream_t st) {
+                 int node_wg, const RedRec *grec, int64_t grec_count, double *gred,
+                 hipStream_t st) {
   int64_t blocks = std::max<int64_t>((seg_cap * 8 + 255) / 256, node_wg);
   if (blocks > 8192) blocks = 8192;
   scan_exclusive(smark, smap, smap_cap, &tot[5], &tot[2], lb, 1, st);
@@ -772,43 +778,17 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
   APIC_LAUNCH(k_seg_slots, dim3((unsigned)blocks), dim3(256), 0, st, seg, cnt, seg_cap, slay,
               blay, smark, smap, smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap,
               item_cap, (uint32_t *)g.mass, (uint32_t *)g.buf[0], (uint32_t *)g.buf[1],
-              (uint32_t *)g.bmass, tbytes / 4);
+              (uint32_t *)g.bmass, tbytes / 4, grec, grec_count, gred);
 }
 
-// Block-wide reduction of 256 records: one set of atomics per block when all
-// its records name one scene, per record otherwise.
+// One workgroup per 256 records (skipped when the step has an error).
 __global__ __launch_bounds__(256) void k_reduce_red(const RedRec *rec, int64_t count_cap,
                                                     const int32_t *count_dev,
                                                     const Counters *cnt, double *out) {
-  __shared__ double part[kRed][4];
-  __shared__ int32_t key0;
-  if (cnt && cnt->err) return;
+  if (cnt && cnt->err) return;  // workgroup-uniform
   int64_t count = count_dev ? (int64_t)*count_dev : count_cap;
   if (count > count_cap) count = count_cap;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int key = -1;
-  if (i < count) key = rec[i].key;
-  if (threadIdx.x == 0) key0 = -2;
-  __syncthreads();
-  if (key >= 0) atomicCAS(&key0, -2, key);
-  __syncthreads();
-  const int k0 = key0;
-  const bool uniform = __syncthreads_and(key < 0 || key == k0);
-  if (k0 < 0) return;
-  if (uniform) {
-    const int wave = threadIdx.x >> 6;
-    for (int c = 0; c < kRed; ++c) {
-      double v = wave_sum(key >= 0 ? rec[i].v[c] : 0.0);
-      if ((threadIdx.x & 63) == 0) part[c][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kRed)
-      atomicAdd(&out[(int64_t)k0 * kRed + threadIdx.x],
-                part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
-                    part[threadIdx.x][3]);
-  } else if (key >= 0) {
-    for (int c = 0; c < kRed; ++c) atomicAdd(&out[(int64_t)key * kRed + c], rec[i].v[c]);
-  }
+  reduce_rec_block(rec, (int64_t)blockIdx.x * blockDim.x, count, out);
 }
 
 void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *count_dev,

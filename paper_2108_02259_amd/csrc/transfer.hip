@@ -434,7 +434,7 @@ __device__ __forceinline__ void load_vel_tile(T (*tile)[kTileSize], const T *q, 
   }
 }
 
-template <typename T, int NC>
+template <typename T, int NC, bool ZERO = true>
 __device__ __forceinline__ void flush_tile(T (*tile)[kTileSize], T *buf, const int32_t *slot,
                                            int comps_in_buf) {
   const int lane = threadIdx.x & 63;
@@ -445,7 +445,7 @@ __device__ __forceinline__ void flush_tile(T (*tile)[kTileSize], T *buf, const i
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const T v = tile[q][li];
-      tile[q][li] = T(0);
+      if (ZERO) tile[q][li] = T(0);
       if (v != T(0) && s >= 0)
         unsafeAtomicAdd(&buf[((int64_t)s * comps_in_buf + q) * kNodesPerBlock + lane], v);
     }
@@ -551,10 +551,10 @@ __device__ __forceinline__ void group_tables(const StepArgs &a, GroupLds<G> &gl)
 }
 
 // Sum the covering waves' tiles per node (wave order) and add each nonzero
-// sum once to the global buffer; the tiles read are left zero.  Wave v of
+// sum once to the global buffer; with ZERO the tiles read are left zero.  Wave v of
 // the workgroup takes node blocks J = v, v + G, ..., one node per lane, so
 // everything about J is wave-uniform.
-template <typename T, int G, int NC>
+template <typename T, int G, int NC, bool ZERO = true>
 __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const GroupLds<G> &gl,
                                             T *buf, int comps_in_buf) {
   const int lane = fresh_lane();
@@ -575,7 +575,7 @@ __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const Gro
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         sum[q] += tiles[w][q][li];
-        tiles[w][q][li] = T(0);
+        if (ZERO) tiles[w][q][li] = T(0);
       }
     }
     const int s = __builtin_amdgcn_readfirstlane(gl.slot[J]);
@@ -589,13 +589,15 @@ __device__ __forceinline__ void group_flush(T (*tiles)[NC][kTileSize], const Gro
 
 // Flush of a group's shared-grid tiles: each wave's own tile when G = 1,
 // else the merged tiles (all threads of the workgroup take part).
-template <typename T, int G, int NC>
+// ZERO: leave the tiles read zero (for kernels that accumulate the next item
+// into them); the rounds reload every tile entry G2P reads, so they skip it.
+template <typename T, int G, int NC, bool ZERO = true>
 __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kTileSize],
                                             GroupLds<G> &gl, bool flushes, int seg_index,
                                             T *buf, int comps_in_buf) {
   if (G == 1) {
     wave_sync();
-    if (flushes) flush_tile<T, NC>(tiles[0], buf, a.seg[seg_index].sslot, comps_in_buf);
+    if (flushes) flush_tile<T, NC, ZERO>(tiles[0], buf, a.seg[seg_index].sslot, comps_in_buf);
     wave_sync();
   } else {
     const int wave = wave_id();
@@ -610,7 +612,7 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
     __syncthreads();
     group_tables<G>(a, gl);
     __syncthreads();
-    group_flush<T, G, NC>(tiles, gl, buf, comps_in_buf);
+    group_flush<T, G, NC, ZERO>(tiles, gl, buf, comps_in_buf);
     __syncthreads();
   }
 }
@@ -931,7 +933,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           LDS_ORDER();
         }
       }
-      flush_group<T, G, 3>(a, tile, gl, member, it.seg, gnext, 3);
+      flush_group<T, G, 3, false>(a, tile, gl, member, it.seg, gnext, 3);
     }
     wave_sync();
   }
