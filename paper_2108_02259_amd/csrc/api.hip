@@ -242,8 +242,8 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kValsB, sizeof(uint32_t) * n));
   TRY(W.ensure(kGhist, sizeof(uint32_t) * radix_hist_words(n)));
   const int64_t lbcap = std::max<int64_t>(
-      scan_tile_count(std::max<int64_t>({n, P.smap_cap, P.bmap_cap, 256 * ntiles})),
-      scan_tile_count(P.seg_cap, 1));
+      {scan_tile_count(std::max<int64_t>({n, 256 * ntiles})),
+       scan_tile_count(P.smap_cap) + scan_tile_count(P.bmap_cap), scan_tile_count(P.seg_cap, 1)});
   TRY(W.ensure(kLbFlags, sizeof(uint64_t) * lbcap));
   TRY(W.ensure(kLbState, sizeof(uint32_t) * 2));
   TRY(W.ensure(kT, T * 3 * n));

@@ -30,6 +30,12 @@ void lookback_init(const Lookback &lb, hipStream_t st);
 // written to *total (int64).  mode 1 writes -1 where in[i] == 0 (slot maps).
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_t *n_dev,
                     int64_t *total, const Lookback &lb, int mode, hipStream_t st);
+// Two such scans in one launch (flags for scan_tile_count(cap0) +
+// scan_tile_count(cap1) tiles).
+void scan_exclusive_pair(const int32_t *in0, int32_t *out0, int64_t cap0, const int64_t *n0_dev,
+                         int64_t *total0, const int32_t *in1, int32_t *out1, int64_t cap1,
+                         const int64_t *n1_dev, int64_t *total1, const Lookback &lb, int mode,
+                         hipStream_t st);
 
 void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, int64_t scale,
               hipStream_t st);

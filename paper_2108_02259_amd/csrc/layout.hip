@@ -773,8 +773,8 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
                  hipStream_t st) {
   int64_t blocks = std::max<int64_t>((seg_cap * 8 + 255) / 256, node_wg);
   if (blocks > 8192) blocks = 8192;
-  scan_exclusive(smark, smap, smap_cap, &tot[5], &tot[2], lb, 1, st);
-  scan_exclusive(bmark, bmap, bmap_cap, &tot[6], &tot[3], lb, 1, st);
+  scan_exclusive_pair(smark, smap, smap_cap, &tot[5], &tot[2], bmark, bmap, bmap_cap, &tot[6],
+                      &tot[3], lb, 1, st);
   APIC_LAUNCH(k_seg_slots, dim3((unsigned)blocks), dim3(256), 0, st, seg, cnt, seg_cap, slay,
               blay, smark, smap, smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap,
               item_cap, (uint32_t *)g.mass, (uint32_t *)g.buf[0], (uint32_t *)g.buf[1],

@@ -149,22 +149,15 @@ __device__ uint32_t wave_lookback(const uint64_t *flags, int64_t stride, int t, 
   return excl;
 }
 
-// ITEMS consecutive elements per thread (kScanItems for long arrays; 1 for
-// short tables whose per-element work is heavy, so that they spread over
-// more workgroups).
-template <typename In, typename Out, int ITEMS = kScanItems>
-__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, int64_t n_cap,
-                                                               const int64_t *n_dev,
-                                                               int64_t *total, uint64_t *flags,
-                                                               uint32_t *state) {
+// Tile t (of tiles 0..last holding data) of one scan: reads its inputs,
+// publishes its aggregate, looks back for its prefix in flags[0, t) and
+// writes its outputs.  The caller signals lb_finish afterwards.
+template <typename In, typename Out, int ITEMS>
+__device__ __forceinline__ void scan_tile(const In &in, const Out &out, int64_t n, int t, int last,
+                                          int64_t *total, uint64_t *flags, uint32_t epoch) {
   __shared__ int lds[kScanThreads / 64];
   __shared__ uint32_t s_excl;
-  const int64_t n = dev_count(n_cap, n_dev);
-  const int t = blockIdx.x;
-  const uint32_t epoch = lb_epoch(state);
   constexpr int64_t kTile = (int64_t)kScanThreads * ITEMS;
-  const int last = n > 0 ? (int)((n - 1) / kTile) : 0;  // last tile holding data
-  if (t > last) return;  // past the live count: takes no part
   const int64_t base = (int64_t)t * kTile + (int64_t)threadIdx.x * ITEMS;
   int v[ITEMS];
   int s = 0;
@@ -198,7 +191,54 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, i
     if (i < n) out(i, v[k], run, n);
     run += v[k];
   }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ int scan_last_tile(int64_t n) {
+  constexpr int64_t kTile = (int64_t)kScanThreads * ITEMS;
+  return n > 0 ? (int)((n - 1) / kTile) : 0;  // last tile holding data
+}
+
+// ITEMS consecutive elements per thread (kScanItems for long arrays; 1 for
+// short tables whose per-element work is heavy, so that they spread over
+// more workgroups).
+template <typename In, typename Out, int ITEMS = kScanItems>
+__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(In in, Out out, int64_t n_cap,
+                                                               const int64_t *n_dev,
+                                                               int64_t *total, uint64_t *flags,
+                                                               uint32_t *state) {
+  const int64_t n = dev_count(n_cap, n_dev);
+  const int t = blockIdx.x;
+  const uint32_t epoch = lb_epoch(state);
+  const int last = scan_last_tile<ITEMS>(n);
+  if (t > last) return;  // past the live count: takes no part
+  scan_tile<In, Out, ITEMS>(in, out, n, t, last, total, flags, epoch);
   if (threadIdx.x == 0) lb_finish(state, epoch, last + 1);
+}
+
+// Two independent scans in one launch: workgroups [0, tiles0) take the
+// first (flags[0, tiles0)), the rest the second (flags from tiles0 on).
+// Each scan's tile 0 starts its own look-back chain; one epoch covers both.
+template <typename In, typename Out, int ITEMS = kScanItems>
+__global__ __launch_bounds__(kScanThreads) void k_scan_pair(In in0, Out out0, int64_t cap0,
+                                                            const int64_t *n0_dev, int64_t *total0,
+                                                            In in1, Out out1, int64_t cap1,
+                                                            const int64_t *n1_dev, int64_t *total1,
+                                                            int tiles0, uint64_t *flags,
+                                                            uint32_t *state) {
+  const int64_t n0 = dev_count(cap0, n0_dev), n1 = dev_count(cap1, n1_dev);
+  const int last0 = scan_last_tile<ITEMS>(n0), last1 = scan_last_tile<ITEMS>(n1);
+  const uint32_t epoch = lb_epoch(state);
+  const int b = blockIdx.x;  // workgroup-uniform branches
+  if (b < tiles0) {
+    if (b > last0) return;
+    scan_tile<In, Out, ITEMS>(in0, out0, n0, b, last0, total0, flags, epoch);
+  } else {
+    const int t = b - tiles0;
+    if (t > last1) return;
+    scan_tile<In, Out, ITEMS>(in1, out1, n1, t, last1, total1, flags + tiles0, epoch);
+  }
+  if (threadIdx.x == 0) lb_finish(state, epoch, last0 + last1 + 2);
 }
 
 inline unsigned scan_tiles(int64_t n_cap, int items = kScanItems) {

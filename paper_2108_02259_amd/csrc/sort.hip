@@ -34,6 +34,16 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n_cap, const int64_
               st, a, o, n_cap, n_dev, total, lb.flags, lb.state);
 }
 
+void scan_exclusive_pair(const int32_t *in0, int32_t *out0, int64_t cap0, const int64_t *n0_dev,
+                         int64_t *total0, const int32_t *in1, int32_t *out1, int64_t cap1,
+                         const int64_t *n1_dev, int64_t *total1, const Lookback &lb, int mode,
+                         hipStream_t st) {
+  const unsigned tiles0 = scan_tiles(cap0), tiles1 = scan_tiles(cap1);
+  APIC_LAUNCH((k_scan_pair<ArrayIn, ArrayOut>), dim3(tiles0 + tiles1), dim3(kScanThreads), 0, st,
+              ArrayIn{in0}, ArrayOut{out0, mode}, cap0, n0_dev, total0, ArrayIn{in1},
+              ArrayOut{out1, mode}, cap1, n1_dev, total1, (int)tiles0, lb.flags, lb.state);
+}
+
 // ---------------------------------------------------------------------------
 // fills (kernels, so that they can be captured in graphs)
 // ---------------------------------------------------------------------------
