@@ -192,23 +192,43 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over the 64 lanes, returned to every lane.  Must be called with every
-// lane of the wave active.  Data-parallel-primitive steps: swaps within
-// quads (lane ^ 1, lane ^ 2) and rotations by 4 and 8 within each row of 16
-// give every lane its row's sum; row broadcasts then carry row 0 into row 1
-// and rows 0-1 into rows 2-3, so lane 63 holds the total, which is read out
-// as a scalar.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x124, 0xf>(v);  // row_ror:4
-  v += dpp_f64<0x128, 0xf>(v);  // row_ror:8
-  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+// One halving exchange of wave_sum_spread: slots (2u, 2u+1) differ in bit b
+// of their value index; each lane keeps the slot whose bit equals bit b of
+// its lane (`bit`) and adds the partner lane's other slot, which holds the
+// same value index for the partner's lanes.
+template <int CTRL, int M>
+__device__ __forceinline__ void halve_f64(const double (&in)[2 * M], double (&out)[M], bool bit) {
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    const double a = in[2 * u], b = in[2 * u + 1];
+    const double keep = bit ? b : a, send = bit ? a : b;
+    out[u] = keep + dpp_f64<CTRL, 0xf>(send);
+  }
+}
+
+// Sums over the 64 lanes of K values at once, spread out: lane j (j < K,
+// in every row) returns the total of value j.  Four halving exchanges within
+// each row of 16 (partners lane ^ 1, lane ^ 2, and the rotations by 4 and 8,
+// which pair lanes that agree in their low bits and differ in the next)
+// leave lane l with value (l mod 16) summed over its row; two cross-row
+// exchanges add the other rows.  About 90 instructions for K = 11, where 11
+// separate six-step reductions take about 220.  Every lane of the wave must
+// be active.
+template <int K>
+__device__ __forceinline__ double wave_sum_spread(const double (&q)[K]) {
+  static_assert(K >= 1 && K <= 16, "at most 16 values");
+  const int lane = threadIdx.x & 63;
+  double s0[16], s1[8], s2[4], s3[2], s4[1];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) s0[t] = t < K ? q[t] : 0.0;
+  halve_f64<0xB1, 8>(s0, s1, lane & 1);         // quad_perm [1,0,3,2]: lane ^ 1
+  halve_f64<0x4E, 4>(s1, s2, (lane >> 1) & 1);  // quad_perm [2,3,0,1]: lane ^ 2
+  halve_f64<0x124, 2>(s2, s3, (lane >> 2) & 1); // row_ror:4
+  halve_f64<0x128, 1>(s3, s4, (lane >> 3) & 1); // row_ror:8
+  double v = s4[0];
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
 }
 
 // P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
@@ -253,11 +273,12 @@ __device__ __forceinline__ void reduce_rec_block(const RedRec *rec, int64_t base
   const bool uniform = __syncthreads_and(key < 0 || key == k0);
   if (k0 >= 0) {  // workgroup-uniform
     if (uniform) {
-      const int wave = threadIdx.x >> 6;
-      for (int c = 0; c < kRed; ++c) {
-        const double v = wave_sum(key >= 0 ? rec[i].v[c] : 0.0);
-        if ((threadIdx.x & 63) == 0) part[c][wave] = v;
-      }
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      double q[kRed];
+#pragma unroll
+      for (int c = 0; c < kRed; ++c) q[c] = key >= 0 ? rec[i].v[c] : 0.0;
+      const double v = wave_sum_spread(q);
+      if (lane < kRed) part[lane][wave] = v;
       __syncthreads();
       if (threadIdx.x < kRed)
         atomicAdd(&out[(int64_t)k0 * kRed + threadIdx.x],

@@ -428,11 +428,11 @@ __device__ __forceinline__ void reduce_scene(bool ok, int s, const double q[kRed
     const bool uniform = __ballot(ok && s != s0) == 0;
     if (uniform) {
       key = s0;
+      double qq[kRed];
 #pragma unroll
-      for (int k = 0; k < kRed; ++k) {
-        double v = wave_sum(ok ? q[k] : 0.0);
-        if (lane == 0) rec[wave].v[k] = v;
-      }
+      for (int k = 0; k < kRed; ++k) qq[k] = ok ? q[k] : 0.0;
+      const double v = wave_sum_spread(qq);
+      if (lane < kRed) rec[wave].v[lane] = v;
     } else if (ok) {
 #pragma unroll
       for (int k = 0; k < kRed; ++k) atomicAdd(&direct[(int64_t)s * kRed + k], q[k]);

@@ -1046,11 +1046,8 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
         }
       }
     }
-#pragma unroll
-    for (int c = 0; c < kRed; ++c) {
-      const double v = wave_sum(q[c]);
-      if (lane == 0) rec[w].v[c] = v;
-    }
+    const double v = wave_sum_spread(q);
+    if ((int)lane < kRed) rec[w].v[lane] = v;
     if (lane == 0) rec[w].key = s;
     wave_sync();
   }
