@@ -165,8 +165,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the contact step on a single "
-              "MI355X and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the contact step runs on a single MI355X "
+              "and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
