@@ -38,6 +38,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "contact particle-steps/s (FP32-mixed vs plain FP64) at 2e-5 tol; %HBM peak; p99"
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2 (packed
+# FP32) x 2.4 GHz); the kernels here issue unpacked FP32, whose rate is half.
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Algorithmic flops of one H application per particle with separable weights
+# (P2G about 64 x 14, G2P about 64 x 24, weights about 60).
+ROUND_FLOPS_PER_PARTICLE = 2500
 
 # Algorithmic bytes of one fused round per particle (FP32-mixed; FP64 doubles
 # all but the 4-byte key): read
@@ -70,6 +76,21 @@ def traffic_from_profiles(kernel: str):
     if d.get("source_hash") != source_hash() or d.get("kernel") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def sq_counters_from_profiles(kernel: str):
+    """VALU/LDS utilisation of `kernel` from the committed SQ counter runs, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "round_kernel_sq_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    k = d.get("kernels", {}).get(kernel)
+    if d.get("source_hash") != source_hash() or k is None:
+        return None
+    return {"valu_busy": k["valu_busy"], "lds_active": k["lds_active"],
+            "wave_time_waiting": k["wave_time_waiting"]}
 
 
 def cpu_model():
@@ -274,9 +295,12 @@ def main():
     nodes = info["shared_blocks"] * 64
     alg_bytes = n * ROUND_BYTES_PER_PARTICLE["fp32"] + nodes * ROUND_BYTES_PER_NODE["fp32"]
     achieved = alg_bytes / (round_us * 1e-6) / 1e9
+    alg_flops = n * ROUND_FLOPS_PER_PARTICLE
+    achieved_tf = alg_flops / (round_us * 1e-6) / 1e12
     group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
     round_kernel = f"apic::k_iter<float, false, {group}>"
     traffic = traffic_from_profiles(round_kernel)
+    sq = sq_counters_from_profiles(round_kernel)
     max_drift = drift[0]
     sim.close()
 
@@ -430,11 +454,17 @@ def main():
                                "N=4, resident driver, geometry held at the initial "
                                "configuration (driver dt=0)", "particles": n,
                    "mu": sc.mu, "n_iter": sc.n_iter, "graph": use_graph},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        # the round kernel is bound by vector ALU issue (SQ counters: VALU busy
+        # about 70 % of its cycles, HBM at about a quarter of peak)
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic,
                      "kernel": round_kernel + " (fused G2P + rule + P2G round)",
-                     "kernel_us": round_us, "alg_bytes_per_launch": alg_bytes,
-                     "active_nodes": nodes},
+                     "kernel_us": round_us, "alg_flops_per_launch": alg_flops,
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes,
+                             "active_nodes": nodes},
+                     "sq_counters": sq},
         "cpu_baseline": cpu,
         "fp64": {"value": value64, "unit": "particle-steps/s",
                  "ms_per_step": 1e3 * t64 / args.fp64_steps, "steps": args.fp64_steps,
