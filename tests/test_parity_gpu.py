@@ -101,6 +101,11 @@ CASES = [
                                                   spacing_frac=0.4), 1.0, 3),
     ("dense_cells", lambda: scenes.random_blobs(15, n_bodies=2, side=12, h=1.0,
                                                 spacing_frac=0.3), 0.5, 2),
+    # friction far beyond any tangential change: the rule's sticking limit
+    ("blobs2_N2_mu1e3", lambda: scenes.random_blobs(16, n_bodies=2, side=6, h=0.5), 1e3, 2),
+    # rigid translations, no affine part: contact between uniform fields
+    ("rigid2_N3", lambda: scenes.random_blobs(17, n_bodies=2, side=7, h=0.5,
+                                              random_fields=False), 0.4, 3),
 ]
 
 
