@@ -106,6 +106,10 @@ CASES = [
     # rigid translations, no affine part: contact between uniform fields
     ("rigid2_N3", lambda: scenes.random_blobs(17, n_bodies=2, side=7, h=0.5,
                                               random_fields=False), 0.4, 3),
+    # one body: every node is single-body, the rule still acts on its own normals
+    ("single_body_N3", lambda: scenes.random_blobs(18, n_bodies=1, side=8, h=0.5), 0.3, 3),
+    # four bodies in a row, six series rounds
+    ("blobs4_N6", lambda: scenes.random_blobs(19, n_bodies=4, side=5, h=0.5), 0.4, 6),
 ]
 
 
