@@ -322,7 +322,13 @@ static int check_dense_bounds(const ora_grid *g, int64_t n, const double *x) {
  *   gradient back     B'_p = sum_i N_i(x_p) v_i (x) (x_i - x_p)
  *                                                          (eq. scaledVelGrad)
  *                     E'_p = B'_p D_p^{-1}
- * For the PIC transfer (Section 2.1.1) the affine term is dropped and E' = 0.
+ * For the PIC transfer (Section 2.1.1) the affine term is dropped from the
+ * momentum sum and B is not part of the transferred state: Section 3.1 sets
+ * B_p = 0 in the particle-to-grid sum and removes its evolution, and the PIC
+ * augury of Section 2.2 is the method with no scaled velocity gradient term.
+ * The operator therefore maps {u, E} to {u', E}: the affine part passes
+ * through untouched (so G = H - I has a zero affine part and the series never
+ * changes C).
  * Dinv holds D_p^{-1} per particle (9 per particle, row-major).
  */
 static int apply_H(const ora_grid *g, int64_t n, const double *x,
@@ -372,6 +378,8 @@ static int apply_H(const ora_grid *g, int64_t n, const double *x,
         double e = 0.0;
         if (apic)
           for (int c = 0; c < 3; ++c) e += Bo[3 * a + c] * Dinv[9 * p + 3 * c + b];
+        else
+          e = E[(3 * a + b) * n + p]; /* PIC: B is not evolved */
         Eo[(3 * a + b) * n + p] = e;
       }
   }
@@ -565,13 +573,19 @@ int ora_undesirable(int32_t rule, const double *d, const double *nrm, double mu,
  * affine part can be carried as C.  Unconstrained particles (no normal) get
  * W = 0.  v and C are overwritten with Vhat.
  *
+ * Normals: by default from the body mass fields (compute_normals).  When
+ * nrm_in (3n) is given, those normals are used instead -- the paper's n_p is
+ * an area-weighted outward normal of the finite-element boundary faces at the
+ * node (Section 2.3), which only the caller's mesh knows; a particle whose
+ * given normal is exactly zero is unconstrained.
+ *
  * Optional outputs: nrm_out (3n) the normals, w1_out (12n) the first series
  * field W_1 (v part then C part), uncon_out (n) the unconstrained flags.
  */
 int ora_contact_step(const ora_grid *g, int64_t n, const double *x, double *v,
                      double *C, const double *m, const uint16_t *body,
-                     double mu, int32_t n_iter, double *nrm_out, double *w1_out,
-                     int32_t *uncon_out) {
+                     double mu, int32_t n_iter, const double *nrm_in,
+                     double *nrm_out, double *w1_out, int32_t *uncon_out) {
   if (!valid_grid(g) || n < 0 || !(mu >= 0.0) || n_iter < 0) return ORA_E_INVALID;
   if (n == 0) return ORA_OK;
   if (!x || !v || !C || !m || !body) return ORA_E_INVALID;
@@ -598,8 +612,19 @@ int ora_contact_step(const ora_grid *g, int64_t n, const double *x, double *v,
   }
   rc = inverse_inertia_all(g, n, x, Dinv);
   if (rc) goto done;
-  rc = compute_normals(g, n, x, m, body, nrm, uncon);
-  if (rc) goto done;
+  if (nrm_in) {
+    for (int64_t p = 0; p < n; ++p) {
+      int zero = 1;
+      for (int d = 0; d < 3; ++d) {
+        nrm[d * n + p] = nrm_in[d * n + p];
+        zero &= nrm_in[d * n + p] == 0.0;
+      }
+      uncon[p] = zero;
+    }
+  } else {
+    rc = compute_normals(g, n, x, m, body, nrm, uncon);
+    if (rc) goto done;
+  }
   rc = shared_grid(g, n, x, &G);
   if (rc) goto done;
 

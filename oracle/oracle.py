@@ -90,7 +90,7 @@ def lib():
         L.ora_normals.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
         L.ora_undesirable.argtypes = [ctypes.c_int32, P, P, ctypes.c_double, P]
         L.ora_contact_step.argtypes = [P, ctypes.c_int64, P, P, P, P, P,
-                                       ctypes.c_double, ctypes.c_int32, P, P, P]
+                                       ctypes.c_double, ctypes.c_int32, P, P, P, P]
         L.ora_momentum.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, P, P]
         L.ora_cell_keys.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P,
                                     ctypes.c_int64, P, P, P]
@@ -176,10 +176,13 @@ def undesirable(rule: int, d, nrm, mu: float) -> np.ndarray:
 
 
 def contact_step(grid: Grid, x, v, C, m, body, mu: float, n_iter: int,
-                 want_normals=False, want_w1=False):
-    """The contact step S: returns dict(v, C[, normals, unconstrained][, w1])."""
+                 want_normals=False, want_w1=False, normals_in=None):
+    """The contact step S: returns dict(v, C[, normals, unconstrained][, w1]).
+    normals_in (3, n), optional: the caller's particle normals (zero =
+    unconstrained) instead of the body-mass-gradient normals."""
     x = _f64(x)
     n = x.shape[1]
+    nin = None if normals_in is None else _f64(normals_in, (3, n))
     v = _f64(v, (3, n)).copy()
     C = _f64(C, (9, n)).copy()
     m = _f64(m, (n,))
@@ -189,8 +192,8 @@ def contact_step(grid: Grid, x, v, C, m, body, mu: float, n_iter: int,
     w1 = np.zeros((12, n)) if want_w1 else None
     g = grid.c()
     _check(lib().ora_contact_step(ctypes.byref(g), n, _ptr(x), _ptr(v), _ptr(C), _ptr(m),
-                                  _ptr(body), float(mu), int(n_iter), _ptr(nrm), _ptr(w1),
-                                  _ptr(unc)))
+                                  _ptr(body), float(mu), int(n_iter), _ptr(nin), _ptr(nrm),
+                                  _ptr(w1), _ptr(unc)))
     out = {"v": v, "C": C}
     if want_normals:
         out["normals"] = nrm

@@ -276,13 +276,38 @@ def request_stream(lam: float, duration: float, seed: int = SEED_BASE + 5,
     return out
 
 
+def box_face_normals(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Particle normals of an nx x ny x nz lattice box (the ordering of
+    lattice_box) as a finite-element mesh would give them: the lattice is read
+    as a hexahedral mesh whose nodes are the particles, and each boundary node
+    gets the area-weighted sum of the outward normals of the boundary faces
+    around it, normalised.  On a regular lattice the faces around a node have
+    equal area, so a face node gets its face's normal, an edge node the
+    normalised sum of its two faces' normals and a corner node that of three.
+    Interior nodes touch no boundary face and get a zero normal.  (Mesh
+    geometry only: this is an input the caller supplies, not part of the
+    contact method.)"""
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    idx = (i.ravel(), j.ravel(), k.ravel())
+    nrm = np.zeros((3, nx * ny * nz))
+    for d, (q, hi) in enumerate(zip(idx, (nx, ny, nz))):
+        nrm[d] -= (q == 0)
+        nrm[d] += (q == hi - 1)
+    length = np.sqrt((nrm ** 2).sum(0))
+    on = length > 0
+    nrm[:, on] /= length[on]
+    return nrm
+
+
 def random_blobs(seed: int, n_bodies: int = 2, side: int = 5, h: float = 1.0,
                  jitter_frac: float = 0.1, spacing_frac: float = 1.0, gap_frac: float = 0.5,
-                 random_fields: bool = True, cell_offset: float = 0.5) -> Scene:
+                 random_fields: bool = True, cell_offset: float = 0.5,
+                 uniform_mass: bool = False) -> Scene:
     """Small test scenes: n_bodies lattice cubes of side^3 particles in a row
     along x, touching (gap_frac*h between facing planes), with random
     velocities and affine matrices (or zero C when random_fields is False),
-    random masses in [0.5, 1.5]."""
+    random masses in [0.5, 1.5] (or, with uniform_mass, one mass per body from
+    {1, 0.75, 0.5, 1.25}, exact binary fractions)."""
     rng = np.random.default_rng(seed)
     sp = spacing_frac * h
     parts = []
@@ -298,8 +323,9 @@ def random_blobs(seed: int, n_bodies: int = 2, side: int = 5, h: float = 1.0,
         else:
             v = np.repeat(rng.normal(size=(3, 1)), n, 1)
             C = np.zeros((9, n))
-        parts.append((pts, v, C, rng.uniform(0.5, 1.5, size=n),
-                      np.full(n, bid, dtype=np.uint16)))
+        mass = (np.full(n, (1.0, 0.75, 0.5, 1.25)[bid % 4]) if uniform_mass
+                else rng.uniform(0.5, 1.5, size=n))
+        parts.append((pts, v, C, mass, np.full(n, bid, dtype=np.uint16)))
     return _assemble(parts, h, name="blobs")
 
 

@@ -331,9 +331,11 @@ def test_two_particle_pic_closed_form(X):
     x[0] = [X, -X]
     u = np.zeros((3, 2))
     u[0] = [0.9, -0.9]
-    uo, Eo = ora.apply_H(g, x, np.ones(2), u, np.zeros((9, 2)))
+    E = np.zeros((9, 2))
+    E[0] = [0.35, -0.2]                      # ignored by the transfer, passed through
+    uo, Eo = ora.apply_H(g, x, np.ones(2), u, E)
     assert uo[0, 0] - 0.9 == pytest.approx((X * X - 1.0) * 0.9, abs=1e-14)
-    assert np.all(Eo == 0.0)
+    np.testing.assert_array_equal(Eo, E)
 
 
 # --------------------------------------------------------------------------

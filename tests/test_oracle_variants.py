@@ -1,0 +1,301 @@
+"""Pins for the parts of the FP64 CPU oracle beyond the default APIC/Coulomb
+step: the energy weight of the affine mode, the separation-only rule of
+Section 2.3, PIC transfers (Sections 2.1.1, 2.2, 3.1) and caller-supplied
+normals (Section 2.3).  Each test checks the oracle against a closed form,
+an exact special case or brute force, not against its own formulas.
+
+Paper: Tupek, Koester, Mosby, arXiv 2108.02259.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as ora
+from paper_2108_02259_amd import scenes
+
+
+def grid(h=1.0, **kw):
+    return ora.Grid(h=h, **kw)
+
+
+# --------------------------------------------------------------------------
+# Energy: the affine mode's weight is the stencil's second moment
+# --------------------------------------------------------------------------
+
+def stencil_energy(x, v, C, m, h, origin=(0.0, 0.0, 0.0)):
+    """1/2 m sum_i N_i(x) |v + C (x_i - x)|^2 over the 64 stencil nodes, by
+    brute force: the kinetic energy of the particle's affine velocity spread
+    over the nodes it touches with the weights of its basis."""
+    per_axis = []
+    for d in range(3):
+        xi = (x[d] - origin[d]) / h
+        first, w, _ = ora.shape_1d(ora.KERNEL_QUAD, xi)
+        per_axis.append([(w[k], origin[d] + h * (first + k) - x[d]) for k in range(4)])
+    Cm = np.asarray(C).reshape(3, 3)
+    e = 0.0
+    for (wa, dxa), (wb, dxb), (wc, dxc) in itertools.product(*per_axis):
+        u = np.asarray(v) + Cm @ np.array([dxa, dxb, dxc])
+        e += wa * wb * wc * (u @ u)
+    return 0.5 * m * e
+
+
+@pytest.mark.parametrize("h", [1.0, 0.37, 2.5])
+def test_energy_affine_weight_is_the_stencil_second_moment(h):
+    """E = 1/2 sum m (|v|^2 + (h^2/2) |C|_F^2) equals the brute-force stencil
+    sum for random particles: the weight h^2/2 is the eigenvalue of D_p
+    (Appendix B), so a wrong factor (h^2, h^2/4, 1) fails."""
+    rng = np.random.default_rng(7)
+    origin = (0.3, -1.1, 0.05)
+    for _ in range(20):
+        x = rng.uniform(-5, 5, size=(3, 1))
+        v = rng.normal(size=(3, 1))
+        C = rng.normal(size=(9, 1)) * 3.0 / h
+        m = rng.uniform(0.2, 3.0, size=1)
+        e_ora = ora.momentum(x, v, C, m, h)["E"]
+        e_bf = stencil_energy(x[:, 0], v[:, 0], C[:, 0], m[0], h, origin)
+        assert e_ora == pytest.approx(e_bf, rel=1e-13)
+
+
+def test_energy_of_a_rigid_spin():
+    """A rigid spin (v = w x r, C = [w]_x) carries E = 1/2 sum m (|v|^2 +
+    h^2 |w|^2): |[w]_x|_F^2 = 2 |w|^2."""
+    rng = np.random.default_rng(8)
+    h = 0.5
+    x = rng.uniform(-3, 3, size=(3, 40))
+    w = np.array([0.3, -1.2, 0.7])
+    v = np.cross(np.broadcast_to(w, x.T.shape), x.T).T
+    C = np.repeat(scenes.skew(w).reshape(9, 1), 40, 1)
+    m = rng.uniform(0.5, 1.5, size=40)
+    e = ora.momentum(x, v, C, m, h)["E"]
+    ref = 0.5 * (m * ((v ** 2).sum(0) + h * h * (w @ w))).sum()
+    assert e == pytest.approx(ref, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Section 2.3: the separation-only rule, exact special cases
+# --------------------------------------------------------------------------
+
+def head_on_cubes(speed, side=6, gap_cells=1):
+    """Two equal jitter-free lattice cubes at cell centres (h = 1, exact
+    binary weights), moving along x with velocities +speed (left cube) and
+    -speed (right cube); speed > 0 approaches, speed < 0 separates.  C = 0."""
+    rng = np.random.default_rng(0)
+    a = scenes.lattice_box(side, side, side, 1.0, (0.5, 0.5, 0.5), rng, 0.0)
+    b = scenes.lattice_box(side, side, side, 1.0, (0.5 + side - 1 + gap_cells, 0.5, 0.5),
+                           rng, 0.0)
+    n = a.shape[1]
+    x = np.concatenate([a, b], 1)
+    v = np.zeros((3, 2 * n))
+    v[0, :n], v[0, n:] = speed, -speed
+    body = np.concatenate([np.zeros(n, np.uint16), np.ones(n, np.uint16)])
+    return x, v, np.zeros((9, 2 * n)), np.ones(2 * n), body
+
+
+def first_change(g, x, v, C, m):
+    hv, hC = ora.apply_H(g, x, m, v, C)
+    return hv, hC, hv - v, hC - C
+
+
+def test_separation_rule_approaching_bodies_stay_stuck_exactly():
+    """Approaching bodies: no particle's proposed change pulls it away from
+    its surface (dv.n <= 0 everywhere), so every series field is zero and
+    the step returns H Vbar bitwise for any N -- the sticky APIC transfer.
+    The Coulomb rule, which always takes dC as undesirable, does not."""
+    x, v, C, m, body = head_on_cubes(1.0)
+    g = grid(rule=ora.RULE_SEPARATE)
+    nrm, unc = ora.normals(g, x, m, body)
+    hv, hC, dv, dC = first_change(g, x, v, C, m)
+    dn = (dv * nrm).sum(0)
+    assert not np.any(dn[unc == 0] > 0.0)                 # premise
+    assert np.abs(dv).max() > 0.1 and np.abs(dC).max() > 0.01
+    for N in (1, 3):
+        out = ora.contact_step(g, x, v, C, m, body, 0.5, N)
+        np.testing.assert_array_equal(out["v"], hv)
+        np.testing.assert_array_equal(out["C"], hC)
+    coul = ora.contact_step(grid(), x, v, C, m, body, 0.5, 1)
+    assert np.abs(coul["C"] - hC).max() > 1e-3
+
+
+def test_separation_rule_separating_bodies_closed_form():
+    """Separating bodies in contact: wherever the first change is nonzero it
+    pulls the particle away from its surface (dv.n > 0), so W_1 = (H - I)
+    Vbar whole and, with G = H - I, Vhat_1 = Vbar + G Vbar + G^2 Vbar."""
+    x, v, C, m, body = head_on_cubes(-1.0)
+    g = grid(rule=ora.RULE_SEPARATE)
+    nrm, unc = ora.normals(g, x, m, body)
+    hv, hC, dv, dC = first_change(g, x, v, C, m)
+    changed = (np.abs(dv).max(0) > 0) | (np.abs(dC).max(0) > 0)
+    dn = (dv * nrm).sum(0)
+    assert changed.sum() > 50
+    assert np.all(dn[changed] > 0.0) and not np.any(unc[changed])   # premise
+    g2v, g2C = ora.apply_H(g, x, m, dv, dC)
+    ref_v = v + dv + (g2v - dv)
+    ref_C = C + dC + (g2C - dC)
+    out = ora.contact_step(g, x, v, C, m, body, 0.5, 1)
+    scale = np.abs(v).max()
+    np.testing.assert_allclose(out["v"], ref_v, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(out["C"], ref_C, rtol=0, atol=1e-13 * scale)
+    # the Coulomb rule takes the same field here (dv.n > 0 takes all of it)
+    coul = ora.contact_step(grid(), x, v, C, m, body, 0.5, 1)
+    np.testing.assert_allclose(coul["v"], out["v"], rtol=0, atol=1e-13 * scale)
+
+
+def test_separation_rule_conserves_momentum():
+    sc = scenes.random_blobs(120, n_bodies=3, side=4, h=0.5)
+    g = grid(h=sc.h, rule=ora.RULE_SEPARATE)
+    xref = (0.4, -0.2, 1.1)
+    before = ora.momentum(sc.x, sc.v, sc.C, sc.m, sc.h, xref)
+    out = ora.contact_step(g, sc.x, sc.v, sc.C, sc.m, sc.body, 0.3, 3)
+    after = ora.momentum(sc.x, out["v"], out["C"], sc.m, sc.h, xref)
+    assert np.abs(after["P"] - before["P"]).max() <= 1e-12 * before["P_scale"]
+    assert np.abs(after["L"] - before["L"]).max() <= 1e-12 * before["L_scale"]
+    ref = ora.contact_step(grid(h=sc.h), sc.x, sc.v, sc.C, sc.m, sc.body, 0.3, 3)
+    assert np.abs(out["v"] - ref["v"]).max() > 1e-3     # the rule matters here
+
+
+# --------------------------------------------------------------------------
+# PIC transfers (Sections 2.1.1, 2.2 "PIC augury", 3.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rule", [ora.RULE_COULOMB, ora.RULE_SEPARATE])
+def test_pic_step_leaves_C_and_conserves_linear_momentum(rule):
+    """B is not part of the PIC state (Section 3.1 removes its evolution), so
+    C passes through bitwise; PIC transfers conserve linear momentum
+    (Section 2.1.1) for any series."""
+    sc = scenes.random_blobs(130, n_bodies=3, side=4, h=0.5)
+    g = grid(h=sc.h, transfer=ora.TRANSFER_PIC, rule=rule)
+    for N in (0, 2):
+        out = ora.contact_step(g, sc.x, sc.v, sc.C, sc.m, sc.body, 0.4, N)
+        np.testing.assert_array_equal(out["C"], sc.C)
+        P0 = (sc.m * sc.v).sum(1)
+        P1 = (sc.m * out["v"]).sum(1)
+        scale = (sc.m * np.sqrt((sc.v ** 2).sum(0))).sum()
+        assert np.abs(P1 - P0).max() <= 1e-12 * scale
+        assert np.abs(out["v"] - sc.v).max() > 1e-2
+
+
+def test_pic_reproduces_uniform_translation():
+    """A constant velocity field is reproduced by PIC (partition of unity)."""
+    sc = scenes.random_blobs(131, n_bodies=2, side=4, h=0.5, random_fields=False)
+    v = np.repeat(np.array([[0.7], [-1.3], [0.2]]), sc.n, 1)
+    out = ora.contact_step(grid(h=sc.h, transfer=ora.TRANSFER_PIC), sc.x, v, sc.C, sc.m,
+                           sc.body, 0.3, 2)
+    np.testing.assert_allclose(out["v"], v, rtol=0, atol=1e-14)
+
+
+def test_pic_loses_angular_momentum_where_apic_keeps_it():
+    """Section 2.2: only APIC guarantees angular momentum.  A spinning body
+    through one PIC transfer loses orbital angular momentum (the grid velocity
+    of a rotation is the rotation of the stencil's mass centre, not of the
+    node); APIC conserves L with its spin term."""
+    rng = np.random.default_rng(1)
+    pts = scenes.lattice_box(6, 6, 6, 0.5, (0.25, 0.25, 0.25), rng, 0.05)
+    n = pts.shape[1]
+    c = pts.mean(1, keepdims=True)
+    w = np.array([0.2, -0.5, 1.0])
+    v = np.cross(np.broadcast_to(w, pts.T.shape), (pts - c).T).T
+    C = np.repeat(scenes.skew(w).reshape(9, 1), n, 1)
+    m = np.ones(n)
+    body = np.zeros(n, np.uint16)
+    xref = tuple(c[:, 0])
+    L0 = ora.momentum(pts, v, C, m, 0.5, xref)
+    pic = ora.contact_step(grid(h=0.5, transfer=ora.TRANSFER_PIC), pts, v, C, m, body, 0.0, 0)
+    apic = ora.contact_step(grid(h=0.5), pts, v, C, m, body, 0.0, 0)
+    L_pic = ora.momentum(pts, pic["v"], pic["C"], m, 0.5, xref)
+    L_apic = ora.momentum(pts, apic["v"], apic["C"], m, 0.5, xref)
+    assert np.abs(L_apic["L"] - L0["L"]).max() <= 1e-12 * L0["L_scale"]
+    # PIC: the spin term is constant (C passes through), the orbital part drops
+    assert np.linalg.norm(L_pic["L"]) < np.linalg.norm(L0["L"]) * (1 - 1e-3)
+    assert L_pic["E"] < L0["E"]
+
+
+# --------------------------------------------------------------------------
+# Caller-supplied normals (Section 2.3: area-weighted FE face normals)
+# --------------------------------------------------------------------------
+
+def test_given_mass_gradient_normals_reproduce_the_default_bitwise():
+    sc = scenes.random_blobs(140, n_bodies=3, side=4, h=0.5)
+    g = grid(h=sc.h)
+    nrm, _ = ora.normals(g, sc.x, sc.m, sc.body)
+    a = ora.contact_step(g, sc.x, sc.v, sc.C, sc.m, sc.body, 0.3, 3)
+    b = ora.contact_step(g, sc.x, sc.v, sc.C, sc.m, sc.body, 0.3, 3, normals_in=nrm)
+    np.testing.assert_array_equal(a["v"], b["v"])
+    np.testing.assert_array_equal(a["C"], b["C"])
+
+
+def test_zero_normals_make_every_particle_unconstrained():
+    """With no normal anywhere, W = 0 in every round: the step is H Vbar."""
+    sc = scenes.random_blobs(141, n_bodies=2, side=4, h=0.5)
+    g = grid(h=sc.h)
+    hv, hC = ora.apply_H(g, sc.x, sc.m, sc.v, sc.C)
+    out = ora.contact_step(g, sc.x, sc.v, sc.C, sc.m, sc.body, 0.3, 4,
+                           normals_in=np.zeros((3, sc.n)), want_normals=True)
+    np.testing.assert_array_equal(out["v"], hv)
+    np.testing.assert_array_equal(out["C"], hC)
+    assert out["unconstrained"].all()
+
+
+def test_box_face_normals():
+    nrm = scenes.box_face_normals(3, 4, 5)
+    idx = np.array(list(itertools.product(range(3), range(4), range(5)))).T
+    interior = (idx[0] == 1) & (idx[1] > 0) & (idx[1] < 3) & (idx[2] > 0) & (idx[2] < 4)
+    assert np.all(nrm[:, interior] == 0.0)
+    np.testing.assert_allclose(np.sqrt((nrm[:, ~interior] ** 2).sum(0)), 1.0, atol=1e-15)
+    corner = np.flatnonzero((idx[0] == 0) & (idx[1] == 0) & (idx[2] == 0))[0]
+    np.testing.assert_allclose(nrm[:, corner], -np.ones(3) / np.sqrt(3.0), atol=1e-15)
+
+
+@pytest.mark.parametrize("vt,vn", [(2.0, 0.5), (0.3, 1.2)])
+def test_stick_slip_threshold_with_face_normals(vt, vn):
+    """The block-on-plane stick/slip threshold mu* = v_t / v_n (Section 2.4)
+    with the mesh's face normals in place of the mass-gradient ones: every
+    bottom-face particle of the block away from its edges has n = -e_z, and
+    its first series field keeps the tangential change iff mu >= mu*."""
+    h = 1.0
+    rng = np.random.default_rng(0)
+    side = 5
+    plane = scenes.lattice_box(side + 6, side + 6, 3, h, (0.5, 0.5, 0.5), rng, 0.0)
+    block = scenes.lattice_box(side, side, side, h, (3.5, 3.5, 3.5), rng, 0.0)
+    x = np.concatenate([plane, block], 1)
+    n_p, n_b = plane.shape[1], block.shape[1]
+    v = np.zeros((3, n_p + n_b))
+    v[:, n_p:] = np.array([[vt], [0.0], [-vn]])
+    C = np.zeros((9, n_p + n_b))
+    m = np.concatenate([np.full(n_p, 50.0), np.full(n_b, 1.0)])
+    body = np.concatenate([np.zeros(n_p, np.uint16), np.ones(n_b, np.uint16)])
+    nrm = np.concatenate([scenes.box_face_normals(side + 6, side + 6, 3),
+                          scenes.box_face_normals(side, side, side)], 1)
+    c = n_p + np.flatnonzero((np.abs(block[0] - 5.5) < 1e-9) & (np.abs(block[1] - 5.5) < 1e-9)
+                             & (np.abs(block[2] - 3.5) < 1e-9))[0]
+    np.testing.assert_array_equal(nrm[:, c], [0.0, 0.0, -1.0])
+    g = grid(h=h)
+    hv, _ = ora.apply_H(g, x, m, v, C)
+    dv = hv[:, c] - v[:, c]
+    mu_star = vt / vn
+    assert -dv[0] / dv[2] == pytest.approx(mu_star, rel=1e-12)
+    slip = ora.contact_step(g, x, v, C, m, body, mu_star * (1 - 1e-6), 1, want_w1=True,
+                            normals_in=nrm)["w1"][:3, c]
+    stick = ora.contact_step(g, x, v, C, m, body, mu_star * (1 + 1e-6), 1, want_w1=True,
+                             normals_in=nrm)["w1"][:3, c]
+    assert np.all(stick == 0.0)
+    assert abs(dv[0] - slip[0]) == pytest.approx(mu_star * (1 - 1e-6) * dv[2], rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Unconstrained particles: exact zero mass gradients
+# --------------------------------------------------------------------------
+
+def test_lattice_interior_particles_are_unconstrained():
+    """Jitter-free lattice at cell centres with one mass per body: a particle
+    whose stencil nodes all carry the full body mass (3 cells from every
+    face) has an exactly zero gradient; so does a lone particle at a cell
+    centre (its own mass field is symmetric about it)."""
+    sc = scenes.random_blobs(150, n_bodies=2, side=9, h=1.0, jitter_frac=0.0, gap_frac=1.0,
+                             uniform_mass=True)
+    nrm, unc = ora.normals(grid(), sc.x, sc.m, sc.body)
+    # per body: cells 3..5 on each axis, 27 particles
+    assert unc.sum() == 2 * 27
+    lone = np.array([[40.5], [40.5], [40.5]])
+    _, unc1 = ora.normals(grid(), lone, np.ones(1), np.zeros(1, np.uint16))
+    assert unc1[0] == 1
