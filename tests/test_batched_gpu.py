@@ -47,11 +47,15 @@ def sim_of(ctx, scs, dtype):
     return Sim(ctx, table, dts, xt, vt, Ct, mt, body_dev(body)), table
 
 
-def sampled(scs, rng, k_small=4, k_mid=2, mid_cap=30000):
+def sampled(scs, rng, k_small=4, k_mid=2, mid_cap=30000, k_large=2, large_min=100000):
+    """The smallest scenes, random mid-size ones and random large ones
+    (1e5..2e5 particles)."""
     order = np.argsort([sc.n for sc in scs])
     small = list(order[:k_small])
     mids = [i for i in order if scs[i].n <= mid_cap and i not in small]
-    return small + list(rng.choice(mids, size=k_mid, replace=False))
+    large = [i for i in order if scs[i].n >= large_min]
+    return (small + list(rng.choice(mids, size=k_mid, replace=False))
+            + list(rng.choice(large, size=k_large, replace=False)))
 
 
 def test_full_batch_sampled_scenes_match_oracle_and_alone(ctx):

@@ -139,6 +139,21 @@ def test_contact_step_parity(ctx, name, build, mu, n_iter, dtype, tol):
     scale = rep["P_scale"]
     assert np.abs(np.array(rep["P_before"]) - P_in).max() <= 1e-12 * scale
     assert np.abs(np.array(rep["P_after"]) - P_out).max() <= 1e-12 * scale
+    check_report_sums(rep, x, v, C, m, vg, Cg, sc.h)
+
+
+def check_report_sums(rep, x, v, C, m, vg, Cg, h, origin=(0.0, 0.0, 0.0)):
+    """The reported L (about the grid origin, with the affine spin) and E
+    (with the affine term) equal host FP64 sums over the step's inputs and
+    outputs (summation order aside)."""
+    f = lambda a: np.asarray(a, dtype=np.float64)
+    before = ora.momentum(f(x), f(v), f(C), f(m), h, origin)
+    after = ora.momentum(f(x), f(vg), f(Cg), f(m), h, origin)
+    for key, ref in (("before", before), ("after", after)):
+        assert np.abs(np.array(rep[f"L_{key}"]) - ref["L"]).max() <= 1e-12 * ref["L_scale"]
+        assert rep[f"E_{key}"] == pytest.approx(ref["E"], rel=1e-12)
+    assert rep["P_scale"] == pytest.approx(before["P_scale"], rel=1e-12)
+    assert rep["L_scale"] == pytest.approx(before["L_scale"], rel=1e-12)
 
 
 def test_dense_grid_two_cubes_fp64(ctx):
@@ -227,19 +242,73 @@ def test_batched_matches_oracle_per_scene(ctx):
             assert rep["n_particles"] == sc.n
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.3, 1.0])
 @pytest.mark.parametrize("dtype,tol", [(np.float32, FP32_TOL), (np.float64, FP64_TOL)],
                          ids=["fp32", "fp64"])
-def test_full_size_slab_block(ctx, dtype, tol):
-    """The 1,114,112-particle slab + block at mu = 0.3, 4 iterations: every
-    particle compared with the oracle."""
-    say("full slab_block", dtype.__name__)
-    sc = scenes.slab_block(mu=0.3)
+def test_full_size_slab_block(ctx, dtype, tol, mu):
+    """The 1,114,112-particle slab + block at each of its friction
+    coefficients, 4 iterations: every particle compared with the oracle, and
+    the reported momenta and energy with host sums."""
+    say("full slab_block", dtype.__name__, "mu", mu)
+    sc = scenes.slab_block(mu=mu)
     x, v, C, m = cast_inputs(sc, dtype)
     vg, Cg, rep = gpu_step(ctx, sc, x, v, C, m, sc.mu, sc.n_iter)
     ref = oracle_step(sc, x, v, C, m, sc.mu, sc.n_iter)
     err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
     say(f"  parity error {err:.3e}, blocks {rep['grid_blocks']}")
     assert err <= tol
+    check_report_sums(rep, x, v, C, m, vg, Cg, sc.h)
+
+
+# ---------------------------------------------------------------------------
+# unconstrained particles (zero own-body mass gradient): W = 0, full series
+# rows kept for their work items
+# ---------------------------------------------------------------------------
+
+def unconstrained_scene(seed, side=9, n_lone=3):
+    """Jitter-free lattice cubes at cell centres with one exact mass per body
+    (every weight and mass sum is an exact binary fraction, so a zero
+    gradient is exactly zero in any summation order), random velocities and
+    affine fields, plus lone particles at cell centres as bodies of their
+    own.  Interior particles (3 cells from every face) and the lone ones have
+    no normal."""
+    sc = scenes.random_blobs(seed, n_bodies=2, side=side, h=1.0, jitter_frac=0.0,
+                             gap_frac=1.0, uniform_mass=True)
+    rng = np.random.default_rng(seed + 1)
+    nb = sc.n_bodies
+    xs = [sc.x]
+    for k in range(n_lone):
+        xs.append(np.array([[3.5 + 11.0 * k], [30.5], [3.5]]))
+    x = np.concatenate(xs, 1)
+    v = np.concatenate([sc.v, rng.normal(size=(3, n_lone))], 1)
+    C = np.concatenate([sc.C, rng.normal(size=(9, n_lone))], 1)
+    m = np.concatenate([sc.m, np.full(n_lone, 0.5)])
+    body = np.concatenate([sc.body, np.arange(nb, nb + n_lone, dtype=np.uint16)])
+    return scenes.Scene(x, v, C, m, body, 1.0, name="unconstrained")
+
+
+@pytest.mark.parametrize("n_iter", [0, 1, 4])
+@pytest.mark.parametrize("dtype,tol", [(np.float64, FP64_TOL), (np.float32, FP32_TOL)],
+                         ids=["fp64", "fp32"])
+def test_unconstrained_particles(ctx, dtype, tol, n_iter):
+    say("unconstrained", dtype.__name__, n_iter)
+    sc = unconstrained_scene(160 + n_iter)
+    x, v, C, m = cast_inputs(sc, dtype)
+    g = ora.Grid(h=sc.h)
+    ref = ora.contact_step(g, *(a.astype(np.float64) for a in (x, v, C, m)), sc.body, 0.4,
+                           n_iter, want_normals=True)
+    n_unc = int(ref["unconstrained"].sum())
+    assert n_unc == 2 * 27 + 3
+    vg, Cg, rep = gpu_step(ctx, sc, x, v, C, m, 0.4, n_iter)
+    err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
+    say(f"  parity error {err:.3e}, unconstrained {rep['n_unconstrained']} (oracle {n_unc})")
+    assert err <= tol
+    # N = 0 has no series, so no normals are formed and none is counted
+    assert rep["n_unconstrained"] == (n_unc if n_iter > 0 else 0)
+    check_report_sums(rep, x, v, C, m, vg, Cg, sc.h)
+    # the unconstrained particles' affine rows are carried through the series
+    unc = ref["unconstrained"].astype(bool)
+    assert np.abs(Cg[:, unc]).max() > 0.1
 
 
 TUNINGS = [dict(item_waves_per_cu=w, node_wg_per_cu=nw, xcd_split=x, p2g_group=g)
