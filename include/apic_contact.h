@@ -56,7 +56,9 @@ typedef enum {
   APIC_E_DEVICE = -4,       /* a HIP runtime call failed */
   APIC_E_BUDGET = -5,       /* the context's HBM budget is too small */
   APIC_E_KEY_OVERFLOW = -6, /* more than 2^26 cell blocks in the key space */
-  APIC_E_BODY = -7          /* body id >= the scene's n_bodies */
+  APIC_E_BODY = -7,         /* body id >= the scene's n_bodies */
+  APIC_E_SCRATCH = -8       /* the scene needs more device memory than the fixed
+                               scratch of apic_contact_step_noalloc holds */
 } apic_status;
 
 typedef enum { APIC_FP64 = 0, APIC_FP32_MIXED = 1 } apic_precision;
@@ -118,6 +120,34 @@ apic_status apic_contact_step(apic_ctx *ctx, void *stream, const apic_grid *grid
                               const void *m, const uint16_t *body_id, double mu,
                               int32_t n_iter, apic_precision prec,
                               apic_report *report);
+
+/* Bytes of the fixed device scratch behind apic_contact_step_noalloc. */
+#define APIC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* apic_contact_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, semantics and results, but every work buffer
+ * of the step is carved from one fixed device array of
+ * APIC_NOALLOC_SCRATCH_BYTES per GPU, held from library load until the
+ * process ends.  The call performs no hipMalloc, hipFree or other allocating
+ * call (device or pinned host); its two small readbacks go straight to the
+ * caller's stack.  The caller still owns x, v, C, m and body_id.
+ *  - A scene whose particle arrays cannot fit is refused with APIC_E_SCRATCH
+ *    before any launch; one whose measured grid does not fit is refused with
+ *    APIC_E_SCRATCH after the layout pass, before v and C are touched.
+ *    (Roughly: a compact scene of up to ~3e5 FP32 or ~1.5e5 FP64
+ *    particles fits.)
+ *  - Every call on one GPU shares that GPU's scratch, and each call starts
+ *    by clearing what the step needs zeroed: calls that overlap on one GPU
+ *    (different streams or threads) race and must be serialised by the
+ *    caller.  Calls on apic_contact_step and the other entry points do not
+ *    touch it.
+ *  - It synchronises `stream` like apic_contact_step. */
+apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_grid *grid,
+                                      int64_t n, const void *x, void *v, void *C,
+                                      const void *m, const uint16_t *body_id, double mu,
+                                      int32_t n_iter, apic_precision prec,
+                                      apic_report *report);
 
 /* The contact step of many independent scenes in one set of launches over
  * packed arrays of n_total particles.  scenes (host, n_scenes entries) must

@@ -20,6 +20,8 @@ E_DEVICE = -4
 E_BUDGET = -5
 E_KEY_OVERFLOW = -6
 E_BODY = -7
+E_SCRATCH = -8
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 FP64 = 0
 FP32_MIXED = 1
@@ -65,6 +67,9 @@ SIGNATURES = {
     "apic_contact_step": (ctypes.c_int, [P, P, ctypes.POINTER(Grid), ctypes.c_int64, P, P, P, P,
                                          P, ctypes.c_double, ctypes.c_int32, ctypes.c_int,
                                          ctypes.POINTER(Report)]),
+    "apic_contact_step_noalloc": (ctypes.c_int, [P, P, ctypes.POINTER(Grid), ctypes.c_int64, P, P,
+                                                 P, P, P, ctypes.c_double, ctypes.c_int32,
+                                                 ctypes.c_int, ctypes.POINTER(Report)]),
     "apic_contact_step_batched": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
                                                  ctypes.c_int64, P, P, P, P, P, ctypes.c_int,
                                                  ctypes.POINTER(Report)]),

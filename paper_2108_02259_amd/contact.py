@@ -83,6 +83,20 @@ class Context:
         check(rc, "apic_contact_step")
         return _lib.report_dict(rep) if report else None
 
+    def contact_step_noalloc(self, x, v, C, m, body, h, origin=(0.0, 0.0, 0.0),
+                             dims=(0, 0, 0), mu=0.0, n_iter=1, report=True):
+        """contact_step through the allocation-free entry point (the library's
+        fixed per-GPU scratch; no device allocation by the call)."""
+        n = _check_tensors(x, v, C, m, body)
+        g = make_grid(h, origin, dims)
+        rep = _lib.Report()
+        rc = lib().apic_contact_step_noalloc(self._h, _stream(), ctypes.byref(g), n, _ptr(x),
+                                             _ptr(v), _ptr(C), _ptr(m), _ptr(body), float(mu),
+                                             int(n_iter), precision_of(x),
+                                             ctypes.byref(rep) if report else None)
+        check(rc, "apic_contact_step_noalloc")
+        return _lib.report_dict(rep) if report else None
+
     def contact_step_batched(self, scenes, x, v, C, m, body, report=True):
         """scenes: list of dicts with offset, count, h, origin, dims, mu, n_iter, n_bodies."""
         n = _check_tensors(x, v, C, m, body)

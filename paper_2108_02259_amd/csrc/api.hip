@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "apic_api_internal.h"
@@ -18,6 +19,15 @@ using namespace apic;
 apic_status Workspace::ensure(int id, size_t bytes) {
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~(size_t)255;
+  if (arena) {  // carve: each buffer once per call, 256-byte aligned
+    if (size[id] >= bytes) return APIC_OK;
+    if (bytes > arena_size - held) return APIC_E_SCRATCH;
+    ptr[id] = arena + held;
+    size[id] = bytes;
+    held += bytes;
+    fresh[id] = true;
+    return APIC_OK;
+  }
   if (size[id] >= bytes) return APIC_OK;
   size_t held_after = held - size[id] + bytes;
   if (budget && held_after > budget) return APIC_E_BUDGET;
@@ -40,6 +50,11 @@ apic_status Workspace::ensure(int id, size_t bytes) {
 }
 
 void Workspace::release() {
+  if (arena) {  // nothing was allocated
+    for (int i = 0; i < kNumBufs; ++i) ptr[i] = nullptr, size[i] = 0;
+    held = 0;
+    return;
+  }
   for (int i = 0; i < kNumBufs; ++i) {
     if (ptr[i]) (void)hipFree(ptr[i]);
     ptr[i] = nullptr;
@@ -147,7 +162,14 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
   P.tbytes = prec == APIC_FP64 ? 8 : 4;
   P.n = n;
   P.ns = ns;
-  std::vector<SceneDev> sd(ns);
+  // arena mode (the allocation-free entry point, one scene): the table goes
+  // to the device as a kernel argument, with no host buffer
+  const bool arena = W.arena != nullptr;
+  if (arena && ns != 1) return APIC_E_INVALID;
+  SceneDev one{};
+  std::vector<SceneDev> many;
+  if (!arena) many.resize(ns);
+  SceneDev *sd = arena ? &one : many.data();
   int64_t nb_cap = 0;
   int32_t kmax = 0;
   for (int32_t s = 0; s < ns; ++s) {
@@ -188,10 +210,31 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
   P.cnt = (Counters *)W.ptr[kCounters];
   P.tot = (int64_t *)W.ptr[kTot];
   P.red = (double *)W.ptr[kRedBuf];
+  if (arena) {
+    launch_store_scene(P.sc, one, st);
+    return APIC_OK;
+  }
   TRY(ctx->host_stage(sizeof(SceneDev) * ns));
-  std::memcpy(ctx->stage, sd.data(), sizeof(SceneDev) * ns);
+  std::memcpy(ctx->stage, sd, sizeof(SceneDev) * ns);
   HIPOK(hipMemcpyAsync(P.sc, ctx->stage, sizeof(SceneDev) * ns, hipMemcpyHostToDevice, st));
   HIPOK(hipStreamSynchronize(st));  // the staging buffer is reused right after
+  return APIC_OK;
+}
+
+// Device-to-host copy of a few bytes, completed on return: through the
+// context's pinned staging buffer, or (arena mode, which allocates nothing)
+// straight into the caller's host memory.
+static apic_status read_back(apic_ctx *ctx, const Workspace &W, void *dst, const void *src,
+                             size_t bytes, hipStream_t st) {
+  if (W.arena) {
+    HIPOK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    return APIC_OK;
+  }
+  TRY(ctx->host_stage(bytes));
+  HIPOK(hipMemcpyAsync(ctx->stage, src, bytes, hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  std::memcpy(dst, ctx->stage, bytes);
   return APIC_OK;
 }
 
@@ -421,11 +464,13 @@ static void fill_report(const double *r, int ns, const Counters &c, apic_report 
 // ---------------------------------------------------------------------------
 // the stateless contact step
 // ---------------------------------------------------------------------------
+// The step on workspace W: the context's grow-only arena, or (arena mode)
+// the allocation-free scratch region.  One readback measures the layout,
+// then the step is enqueued and its status read back.
 template <typename T>
-static apic_status step_impl(apic_ctx *ctx, hipStream_t st, const apic_scene *scenes, int32_t ns,
-                             int64_t n, const T *x, T *v, T *C, const T *m, const uint16_t *body,
-                             apic_report *reports) {
-  Workspace &W = ctx->ws;
+static apic_status step_impl(apic_ctx *ctx, Workspace &W, hipStream_t st,
+                             const apic_scene *scenes, int32_t ns, int64_t n, const T *x, T *v,
+                             T *C, const T *m, const uint16_t *body, apic_report *reports) {
   Plan P;
   TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED,
                   nullptr, st));
@@ -436,16 +481,22 @@ static apic_status step_impl(apic_ctx *ctx, hipStream_t st, const apic_scene *sc
   }
   enqueue_prefix<T>(P, st, x, body, nullptr, false);
   Counters c;
-  TRY(ctx->host_stage(sizeof(Counters)));
-  HIPOK(hipMemcpyAsync(ctx->stage, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  HIPOK(hipStreamSynchronize(st));
-  std::memcpy(&c, ctx->stage, sizeof(Counters));
+  TRY(read_back(ctx, W, &c, P.cnt, sizeof(Counters), st));
   TRY(status_from_err(c.err));
   TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0, st));
   TRY(W.ensure(kVbar, sizeof(T) * 12 * n));
   enqueue_sort<T>(P, st, x, body, nullptr);
   enqueue_body<T>(P, st, x, v, C, m, body, (T *)W.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
                   nullptr, nullptr, v, C, true, nullptr);
+  if (W.arena) {  // one scene: the sums and counters on the stack
+    double red[kRed * 2];
+    TRY(read_back(ctx, W, red, P.red, sizeof(red), st));
+    TRY(read_back(ctx, W, &c, P.cnt, sizeof(Counters), st));
+    TRY(status_from_err(c.err));
+    if (c.err) return APIC_E_DEVICE;
+    if (reports) fill_report(red, 1, c, reports);
+    return APIC_OK;
+  }
   const size_t rbytes = sizeof(double) * kRed * 2 * ns;
   TRY(ctx->host_stage(rbytes + sizeof(Counters)));
   HIPOK(hipMemcpyAsync(ctx->stage, P.red, rbytes, hipMemcpyDeviceToHost, st));
@@ -622,6 +673,37 @@ static apic_status sim_step_impl(apic_sim *S, hipStream_t st, int32_t n_steps, i
 }
 
 // ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// A fixed device region (every GPU the library runs on holds its own copy
+// until the process ends).  Host code must not pass `scratch` itself to a
+// kernel -- on the host it is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current (apic_create) and kept in g_scratch_addr.
+constexpr size_t kScratchBytes = (size_t)APIC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+// The calling thread's current device must be `device`.
+static apic_status scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return APIC_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return APIC_E_DEVICE;
+    }
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return APIC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -643,10 +725,13 @@ apic_status apic_create(apic_ctx **out, int device, size_t hbm_budget_bytes) {
     (void)hipGetLastError();
     return APIC_E_DEVICE;
   }
+  void *scr = nullptr;
+  TRY(scratch_address(device, &scr));
   apic_ctx *c = new apic_ctx();
   c->device = device;
   c->ws.budget = hbm_budget_bytes;
   c->cus = prop.multiProcessorCount;
+  c->scratch = scr;
   *out = c;
   return APIC_OK;
 }
@@ -670,6 +755,8 @@ const char *apic_status_string(apic_status s) {
     case APIC_E_BUDGET: return "HBM budget exceeded";
     case APIC_E_KEY_OVERFLOW: return "cell-key space overflow";
     case APIC_E_BODY: return "body id out of range";
+    case APIC_E_SCRATCH:
+      return "scene needs more than the allocation-free entry point's fixed scratch";
   }
   return "unknown status";
 }
@@ -685,10 +772,10 @@ apic_status apic_contact_step_batched(apic_ctx *ctx, void *stream, const apic_sc
   if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   if (prec == APIC_FP64)
-    return step_impl<double>(ctx, st, scenes, n_scenes, n_total, (const double *)x, (double *)v,
-                             (double *)C, (const double *)m, body_id, per_scene);
-  return step_impl<float>(ctx, st, scenes, n_scenes, n_total, (const float *)x, (float *)v,
-                          (float *)C, (const float *)m, body_id, per_scene);
+    return step_impl<double>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const double *)x,
+                             (double *)v, (double *)C, (const double *)m, body_id, per_scene);
+  return step_impl<float>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const float *)x,
+                          (float *)v, (float *)C, (const float *)m, body_id, per_scene);
 }
 
 apic_status apic_contact_step(apic_ctx *ctx, void *stream, const apic_grid *grid, int64_t n,
@@ -704,6 +791,38 @@ apic_status apic_contact_step(apic_ctx *ctx, void *stream, const apic_grid *grid
   s.n_iter = n_iter;
   s.n_bodies = 65536;
   return apic_contact_step_batched(ctx, stream, &s, 1, n, x, v, C, m, body_id, prec, report);
+}
+
+apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_grid *grid,
+                                      int64_t n, const void *x, void *v, void *C, const void *m,
+                                      const uint16_t *body_id, double mu, int32_t n_iter,
+                                      apic_precision prec, apic_report *report) {
+  if (!ctx || !grid) return APIC_E_INVALID;
+  apic_scene s;
+  s.offset = 0;
+  s.count = n;
+  s.grid = *grid;
+  s.mu = mu;
+  s.n_iter = n_iter;
+  s.n_bodies = 65536;
+  TRY(validate_scenes(&s, 1, n));
+  if (n > 0 && (!x || !v || !C || !m || !body_id)) return APIC_E_INVALID;
+  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
+  if (!ctx->scratch) return APIC_E_DEVICE;
+  // the particle arrays alone must fit before anything is launched
+  const int64_t tb = prec == APIC_FP64 ? 8 : 4;
+  if (n > 0 && (uint64_t)n * (uint64_t)(tb * 31 + 24) > kScratchBytes) return APIC_E_SCRATCH;
+  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  Workspace W;  // carves the scratch region; allocates and frees nothing
+  W.arena = (char *)ctx->scratch;
+  W.arena_size = kScratchBytes;
+  W.budget = kScratchBytes;
+  if (prec == APIC_FP64)
+    return step_impl<double>(ctx, W, st, &s, 1, n, (const double *)x, (double *)v,
+                             (double *)C, (const double *)m, body_id, report);
+  return step_impl<float>(ctx, W, st, &s, 1, n, (const float *)x, (float *)v, (float *)C,
+                          (const float *)m, body_id, report);
 }
 
 apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes,
@@ -967,10 +1086,11 @@ apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
     if (timed) prof.begin(st);
     apic_status rc =
         prec == APIC_FP64
-            ? step_impl<double>(ctx, st, scenes, n_scenes, n_total, (const double *)x,
-                                (double *)tv, (double *)tC, (const double *)m, body_id, nullptr)
-            : step_impl<float>(ctx, st, scenes, n_scenes, n_total, (const float *)x, (float *)tv,
-                               (float *)tC, (const float *)m, body_id, nullptr);
+            ? step_impl<double>(ctx, ctx->ws, st, scenes, n_scenes, n_total,
+                                (const double *)x, (double *)tv, (double *)tC,
+                                (const double *)m, body_id, nullptr)
+            : step_impl<float>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const float *)x,
+                               (float *)tv, (float *)tC, (const float *)m, body_id, nullptr);
     if (timed) prof.end(0, st);
     return rc;
   };

@@ -35,13 +35,19 @@ enum BufId {
   kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
 };
 
-// Grow-only device buffers, bounded by an HBM budget.
+// Grow-only device buffers, bounded by an HBM budget.  In arena mode (arena
+// set) buffers are carved one after another from a fixed device region
+// instead of being allocated: nothing is allocated or freed, every buffer
+// counts as fresh, and a request beyond the region fails with
+// APIC_E_SCRATCH.
 struct Workspace {
   void *ptr[kNumBufs] = {};
   size_t size[kNumBufs] = {};
   bool fresh[kNumBufs] = {};  // (re)allocated since the caller last cleared it
   size_t held = 0;
   size_t budget = 0;
+  char *arena = nullptr;      // arena mode: the region, its size and the bytes carved
+  size_t arena_size = 0;
   apic_status ensure(int id, size_t bytes);
   void release();
 };
@@ -134,6 +140,7 @@ void launch_unpermute(const uint32_t *orig, int64_t n, const T *x_sorted, const 
 struct apic_ctx {
   int device = 0;
   int cus = 0;
+  void *scratch = nullptr;  // device address of this device's allocation-free scratch
   apic::Workspace ws;
   // launch tuning per (precision, floor(log2 n))
   std::map<std::pair<int, int>, apic_tuning> tuning;

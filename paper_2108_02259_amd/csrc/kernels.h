@@ -39,6 +39,9 @@ void scan_exclusive_pair(const int32_t *in0, int32_t *out0, int64_t cap0, const 
 
 void fill_i32(int32_t *p, int32_t value, int64_t n_cap, const int64_t *n_dev, int64_t scale,
               hipStream_t st);
+// One scene record written by a kernel that takes it as an argument (no host
+// staging buffer).
+void launch_store_scene(SceneDev *dst, const SceneDev &s, hipStream_t st);
 void fill_bytes_zero(void *p, int64_t bytes, hipStream_t st);
 void fill_zero_f(void *p, int64_t elems_cap, const int32_t *n_dev, int64_t per, int elem_bytes,
                  hipStream_t st);

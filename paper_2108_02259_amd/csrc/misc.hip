@@ -39,6 +39,12 @@ void launch_step_end(const Counters *cnt, const double *red, int ns, SimDev *dev
   APIC_LAUNCH(k_step_end, dim3(g), dim3(256), 0, st, cnt, red, ns, dev, drift);
 }
 
+__global__ void k_store_scene(SceneDev *dst, SceneDev s) { *dst = s; }
+
+void launch_store_scene(SceneDev *dst, const SceneDev &s, hipStream_t st) {
+  APIC_LAUNCH(k_store_scene, dim3(1), dim3(1), 0, st, dst, s);
+}
+
 __global__ void k_iota(uint32_t *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
