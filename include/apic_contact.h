@@ -57,8 +57,11 @@ typedef enum {
   APIC_E_BUDGET = -5,       /* the context's HBM budget is too small */
   APIC_E_KEY_OVERFLOW = -6, /* more than 2^26 cell blocks in the key space */
   APIC_E_BODY = -7,         /* body id >= the scene's n_bodies */
-  APIC_E_SCRATCH = -8       /* the scene needs more device memory than the fixed
+  APIC_E_SCRATCH = -8,      /* the scene needs more device memory than the fixed
                                scratch of apic_contact_step_noalloc holds */
+  APIC_E_RESIZE = -9,       /* a planned step outgrew its plan's capacities (the
+                               step did nothing; create a new plan) */
+  APIC_E_TABLE = -10        /* a device scene table does not match its plan */
 } apic_status;
 
 typedef enum { APIC_FP64 = 0, APIC_FP32_MIXED = 1 } apic_precision;
@@ -71,29 +74,54 @@ typedef struct {
   int32_t dims[3];
 } apic_grid;
 
-/* Momentum report of one step (all FP64).  L is taken about the grid origin
- * and includes the affine spin (h^2/2) (C_zy - C_yz, C_xz - C_zx, C_yx - C_xy)
- * that the APIC transfers conserve (Section 2.1.2); E = 1/2 sum m (|v|^2 +
- * (h^2/2)|C|_F^2).  P_scale = sum m |v|, L_scale = sum m (|x - o||v| +
- * (h^2/2)|C|_F) normalise drift when the totals vanish. */
+/* Momentum report of one step (all FP64).  "before" is the step's input
+ * Vbar, "after" its output Vhat.  L is taken about the scene's x_ref (the
+ * grid origin for the single-scene calls) and includes the affine spin
+ * (h^2/2) (C_zy - C_yz, C_xz - C_zx, C_yx - C_xy) that the APIC transfers
+ * conserve (Section 2.1.2); E = 1/2 sum m (|v|^2 + (h^2/2)|C|_F^2).
+ * P_scale = sum m |v|, L_scale = sum m (|x - x_ref||v| + (h^2/2)|C|_F)
+ * normalise drift when the totals vanish. */
 typedef struct {
   double P_before[3], P_after[3];
   double L_before[3], L_after[3];
   double E_before, E_after;
   double P_scale, L_scale;
   int64_t n_particles;
-  int64_t n_unconstrained; /* particles with a zero mass gradient */
-  int64_t grid_blocks;     /* active 4x4x4 node blocks of the shared grid */
+  int64_t n_unconstrained;     /* particles without a contact normal (zero
+                                  own-body mass gradient, or a zero given
+                                  normal); 0 when N = 0 (no series, no normals) */
+  int64_t grid_blocks;         /* active 4x4x4 node blocks of the shared grid */
+  int32_t max_bodies_per_node; /* most bodies with mass at one grid node */
+  int32_t reserved;
 } apic_report;
+
+/* Scene flags: variants of the method the paper contrasts. */
+enum {
+  /* PIC transfers (Section 2.1.1; the "PIC augury" of Section 2.2): the
+   * particle-to-grid sum drops the affine term and C is not part of the
+   * transferred state, so C passes through the step unchanged.  Linear
+   * momentum is conserved, angular momentum in general is not. */
+  APIC_PIC = 1,
+  /* The separation-only rule of Section 2.3 instead of the Coulomb rule of
+   * Section 2.4: W = (dv, dC) where dv.n > 0, else 0. */
+  APIC_RULE_SEPARATE = 2
+};
 
 /* One scene of a packed batch: its particles are [offset, offset + count) of
  * the packed arrays, its body ids are < n_bodies. */
 typedef struct {
   int64_t offset, count;
   apic_grid grid;
-  double mu;       /* Coulomb coefficient, >= 0 */
-  int32_t n_iter;  /* augury iterations N >= 0 (N + 1 applications of H) */
+  double mu;         /* Coulomb coefficient, >= 0 (Section 2.4) */
+  int32_t n_iter;    /* augury iterations N >= 0 (N + 1 applications of H) */
   int32_t n_bodies;
+  int32_t flags;     /* APIC_PIC | APIC_RULE_SEPARATE, 0 = APIC + Coulomb */
+  int32_t reserved;  /* 0 */
+  double accel[3];   /* mechanical acceleration a of the scene (Section 2.2:
+                        the resident driver and the server predict
+                        Vbar = V + dt {a, 0} before each contact step; the
+                        stateless calls take Vbar itself and ignore it) */
+  double x_ref[3];   /* reference point of the reported angular momentum */
 } apic_scene;
 
 typedef struct apic_ctx apic_ctx;
@@ -150,15 +178,64 @@ apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_gr
                                       apic_report *report);
 
 /* The contact step of many independent scenes in one set of launches over
- * packed arrays of n_total particles.  scenes (host, n_scenes entries) must
- * tile [0, n_total) in increasing offset order.  per_scene (host, optional,
- * n_scenes entries) receives each scene's report. */
+ * packed arrays of n_total particles, each with its own grid, mu, N and
+ * flags.  scenes (host, n_scenes entries) must tile [0, n_total) in
+ * increasing offset order.  normals (device, optional, [3][n_total] of the
+ * precision's type): the caller's particle normals -- the paper's n_p, an
+ * area-weighted outward normal of the finite-element boundary faces at the
+ * node (Section 2.3), which only the caller's mesh knows; a zero normal
+ * marks an unconstrained particle -- used instead of the body-mass-gradient
+ * normals.  per_scene (host, optional, n_scenes entries) receives each
+ * scene's report.  Synchronises `stream` (twice: the layout is measured
+ * before the step is sized); apic_plan_step is the asynchronous form. */
 apic_status apic_contact_step_batched(apic_ctx *ctx, void *stream,
                                       const apic_scene *scenes, int32_t n_scenes,
                                       int64_t n_total, const void *x, void *v,
                                       void *C, const void *m,
-                                      const uint16_t *body_id, apic_precision prec,
-                                      apic_report *per_scene);
+                                      const uint16_t *body_id, const void *normals,
+                                      apic_precision prec, apic_report *per_scene);
+
+/* ------------------------------------------------------------------------
+ * Planned (asynchronous, graph-capturable) contact step.
+ *
+ * apic_contact_step(_batched) measure each call's layout with a readback
+ * before sizing it.  A plan measures a batch once and keeps device buffers
+ * sized with headroom, so that apic_plan_step enqueues the whole step on the
+ * caller's stream with no host synchronisation, no host memory access and
+ * no allocation -- it can be captured into a HIP graph and replayed.  The
+ * device checks every capacity; a step that would exceed one does nothing
+ * (v and C untouched) and reports APIC_E_RESIZE through status_dev.
+ * ------------------------------------------------------------------------ */
+typedef struct apic_plan apic_plan;
+
+/* Measure the batch (same arguments and rules as apic_contact_step_batched;
+ * x and body_id are read, one synchronisation) and size a plan for it with
+ * capacities `headroom` >= 1 times the measured ones.  The plan keeps a
+ * device copy of the scene table. */
+apic_status apic_plan_create(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                             int32_t n_scenes, int64_t n_total, const void *x,
+                             const uint16_t *body_id, apic_precision prec, double headroom,
+                             apic_plan **out);
+
+/* Enqueue the contact step of the plan's batch on `stream` (the problem
+ * statement of Section 2.2, V <- S(Vbar), per scene) and return at once.
+ * x, v, C, m, body_id, normals as for apic_contact_step_batched (device,
+ * n_total particles of the plan's precision).  Device-side optional
+ * arguments:
+ *  - scenes_dev: a DEVICE scene table for this call (n_scenes entries with
+ *    the plan's offsets, counts and n_bodies; grid, mu, flags, x_ref may
+ *    differ; n_iter at most the plan's largest).  NULL: the plan's table.  A
+ *    mismatch makes the step do nothing and reports APIC_E_TABLE.
+ *  - reports_dev: DEVICE array of n_scenes reports, written by the step.
+ *  - status_dev: DEVICE int32, set to the step's apic_status (0 = ok).
+ * The returned status covers host-side argument checks only.  Calls on one
+ * plan must not overlap (they share its buffers). */
+apic_status apic_plan_step(apic_plan *plan, void *stream, const apic_scene *scenes_dev,
+                           const void *x, void *v, void *C, const void *m,
+                           const uint16_t *body_id, const void *normals,
+                           apic_report *reports_dev, int32_t *status_dev);
+
+void apic_plan_destroy(apic_plan *plan);
 
 /* Cell keys and the stable particle order of a batch (the layout step of the
  * contact step, exposed for verification): keys_sorted[i] is the 32-bit cell
@@ -180,9 +257,11 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
  * Resident time stepping.
  *
  * A sim owns device copies of a packed batch of scenes and advances them with
- * the explicit driver of Section 2.2 (tau = dt, no mechanical acceleration):
- * each step takes Vbar = V, sets V <- S(Vbar) (the contact step above, with
- * each scene's mu and N) and then x <- x + dt v.  State stays in HBM between
+ * the explicit driver of Section 2.2 with tau = dt: each step predicts
+ * Vbar = V + dt {a, 0} with the scene's mechanical acceleration a
+ * (apic_scene.accel, constant; the scaled velocity gradient has no mechanical
+ * rate), sets V <- S(Vbar) (the contact step above, with each scene's mu, N
+ * and flags, normals from the body mass gradients) and then x <- x + dt v.  State stays in HBM between
  * steps, in the library's sorted order; apic_sim_read returns it in the
  * caller's original order.  Capacities are sized from the initial state with
  * headroom; a step that would exceed them is replayed after the plan grows,
@@ -243,10 +322,11 @@ apic_status apic_sim_info(apic_sim *sim, int64_t *out);
 
 void apic_sim_destroy(apic_sim *sim);
 
-/* Device bytes a context needs to run one scene of n particles spread over
- * about `blocks_hint` 4x4x4 cell blocks (0 = estimate from n); used by
- * admission control.  Pure host function. */
-int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec);
+/* Device bytes a context needs to step one scene of n particles on `grid`
+ * (host, may be NULL): a dense grid bounds the node blocks by its dims, a
+ * sparse one (or NULL) is estimated from n.  Used by admission control.
+ * Pure host function; -1 for n < 0. */
+int64_t apic_scene_footprint(int64_t n, const apic_grid *grid, apic_precision prec);
 
 /* ------------------------------------------------------------------------
  * Launch tuning.
@@ -320,6 +400,9 @@ typedef struct {
   int32_t admitted;   /* requests that joined at this tick */
   int32_t completed;  /* requests that finished at this tick */
   int32_t queued;     /* requests still waiting after this tick */
+  int32_t deferred;   /* queued requests held back at admission (no room, slot
+                         or budget for the head of the queue) */
+  int32_t failed;     /* requests retired by this tick with an error */
   int64_t particles;  /* particles stepped by this tick */
   int64_t footprint;  /* summed footprint of the requests stepped by this tick */
 } apic_tick;
@@ -344,13 +427,24 @@ apic_status apic_server_submit(apic_server *srv, int64_t tag, const apic_scene *
                                const void *m, const uint16_t *body_id, void *x_out, void *v_out,
                                void *C_out);
 
-/* One tick on `stream`: admit what fits, step every resident request once,
- * copy out and retire the requests that have taken all their steps, and
- * synchronise the stream.  info (host, optional) describes the tick;
- * done_tags (host, optional, max_done entries) receives the tags of the
- * requests completed by this tick (all of them are retired either way). */
+/* One tick on `stream`: admit what fits, step every resident request once
+ * (each with its own mu, N, flags, dt and acceleration: Vbar = V + dt {a, 0},
+ * then V <- S(Vbar), then x <- x + dt v), copy out and retire the requests
+ * that have taken all their steps, and synchronise the stream.  A request
+ * whose particles the device rejects (non-finite values, a body id beyond
+ * its n_bodies, a stencil node outside its dense grid) is retired with that
+ * status and the others are stepped without it, so one bad request never
+ * stalls the rest.  info (host, optional) describes the tick; done_tags and
+ * done_status (host, optional, max_done entries each) receive the tag and
+ * status (APIC_OK when completed, else the error) of every request retired
+ * by this tick (all of them are retired either way). */
 apic_status apic_server_tick(apic_server *srv, void *stream, apic_tick *info, int64_t *done_tags,
-                             int32_t max_done);
+                             int32_t *done_status, int32_t max_done);
+
+/* Withdraw a request by tag: a queued one leaves the queue now, a resident
+ * one leaves at the start of the next tick (its outputs are not written).
+ * APIC_E_INVALID if no such request is queued or resident. */
+apic_status apic_server_cancel(apic_server *srv, int64_t tag);
 
 /* Release the server and its arena (queued requests are dropped). */
 void apic_server_destroy(apic_server *srv);

@@ -21,7 +21,13 @@ E_BUDGET = -5
 E_KEY_OVERFLOW = -6
 E_BODY = -7
 E_SCRATCH = -8
+E_RESIZE = -9
+E_TABLE = -10
 NOALLOC_SCRATCH_BYTES = 64 << 20
+
+# scene flags
+PIC = 1
+RULE_SEPARATE = 2
 
 FP64 = 0
 FP32_MIXED = 1
@@ -38,13 +44,16 @@ class Report(ctypes.Structure):
                 ("E_before", ctypes.c_double), ("E_after", ctypes.c_double),
                 ("P_scale", ctypes.c_double), ("L_scale", ctypes.c_double),
                 ("n_particles", ctypes.c_int64), ("n_unconstrained", ctypes.c_int64),
-                ("grid_blocks", ctypes.c_int64)]
+                ("grid_blocks", ctypes.c_int64), ("max_bodies_per_node", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Scene(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("count", ctypes.c_int64), ("grid", Grid),
                 ("mu", ctypes.c_double), ("n_iter", ctypes.c_int32),
-                ("n_bodies", ctypes.c_int32)]
+                ("n_bodies", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("accel", ctypes.c_double * 3),
+                ("x_ref", ctypes.c_double * 3)]
 
 
 class Tuning(ctypes.Structure):
@@ -55,6 +64,7 @@ class Tuning(ctypes.Structure):
 class Tick(ctypes.Structure):
     _fields_ = [("resident", ctypes.c_int32), ("admitted", ctypes.c_int32),
                 ("completed", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("deferred", ctypes.c_int32), ("failed", ctypes.c_int32),
                 ("particles", ctypes.c_int64), ("footprint", ctypes.c_int64)]
 
 
@@ -71,11 +81,16 @@ SIGNATURES = {
                                                  P, P, P, ctypes.c_double, ctypes.c_int32,
                                                  ctypes.c_int, ctypes.POINTER(Report)]),
     "apic_contact_step_batched": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
-                                                 ctypes.c_int64, P, P, P, P, P, ctypes.c_int,
+                                                 ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int,
                                                  ctypes.POINTER(Report)]),
+    "apic_plan_create": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
+                                        ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
+                                        ctypes.POINTER(P)]),
+    "apic_plan_step": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P]),
+    "apic_plan_destroy": (None, [P]),
     "apic_sort_keys": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
                                       ctypes.c_int64, P, P, ctypes.c_int, P, P]),
-    "apic_scene_footprint": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]),
+    "apic_scene_footprint": (ctypes.c_int64, [ctypes.c_int64, ctypes.POINTER(Grid), ctypes.c_int]),
     "apic_sim_create": (ctypes.c_int, [P, P, ctypes.POINTER(Scene), ctypes.c_int32,
                                        ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int,
                                        ctypes.POINTER(P)]),
@@ -91,7 +106,9 @@ SIGNATURES = {
     "apic_server_submit": (ctypes.c_int, [P, ctypes.c_int64, ctypes.POINTER(Scene), ctypes.c_double,
                                           ctypes.c_int32, P, P, P, P, P, P, P, P]),
     "apic_server_tick": (ctypes.c_int, [P, P, ctypes.POINTER(Tick),
-                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "apic_server_cancel": (ctypes.c_int, [P, ctypes.c_int64]),
     "apic_server_destroy": (None, [P]),
     "apic_get_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
     "apic_set_tuning": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Tuning)]),
@@ -150,7 +167,8 @@ def report_dict(r: Report) -> dict:
             "L_before": list(r.L_before), "L_after": list(r.L_after),
             "E_before": r.E_before, "E_after": r.E_after, "P_scale": r.P_scale,
             "L_scale": r.L_scale, "n_particles": r.n_particles,
-            "n_unconstrained": r.n_unconstrained, "grid_blocks": r.grid_blocks}
+            "n_unconstrained": r.n_unconstrained, "grid_blocks": r.grid_blocks,
+            "max_bodies_per_node": r.max_bodies_per_node}
 
 
 def tuning_dict(t: Tuning) -> dict:

@@ -97,21 +97,20 @@ class Context:
         check(rc, "apic_contact_step_noalloc")
         return _lib.report_dict(rep) if report else None
 
-    def contact_step_batched(self, scenes, x, v, C, m, body, report=True):
-        """scenes: list of dicts with offset, count, h, origin, dims, mu, n_iter, n_bodies."""
+    def contact_step_batched(self, scenes, x, v, C, m, body, normals=None, report=True):
+        """scenes: list of dicts with offset, count, h, origin, dims, mu, n_iter,
+        n_bodies and optionally flags, accel, x_ref (see scene_table).
+        normals: optional (3, n) tensor of the caller's particle normals."""
         n = _check_tensors(x, v, C, m, body)
-        arr = (_lib.Scene * len(scenes))()
-        for i, s in enumerate(scenes):
-            arr[i].offset = int(s["offset"])
-            arr[i].count = int(s["count"])
-            arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
-            arr[i].mu = float(s["mu"])
-            arr[i].n_iter = int(s["n_iter"])
-            arr[i].n_bodies = int(s["n_bodies"])
+        if normals is not None and (tuple(normals.shape) != (3, n) or normals.dtype != x.dtype
+                                    or not normals.is_contiguous()):
+            raise ValueError("normals: expected a contiguous (3, n) tensor of x's dtype")
+        arr = scene_table(scenes)
         reps = (_lib.Report * len(scenes))()
         rc = lib().apic_contact_step_batched(self._h, _stream(), arr, len(scenes), n, _ptr(x),
                                              _ptr(v), _ptr(C), _ptr(m), _ptr(body),
-                                             precision_of(x), reps if report else None)
+                                             _ptr(normals), precision_of(x),
+                                             reps if report else None)
         check(rc, "apic_contact_step_batched")
         return [_lib.report_dict(r) for r in reps] if report else None
 
@@ -149,14 +148,7 @@ class Context:
     def sort_keys(self, scenes, x, body):
         """(sorted keys, permutation) as int64 cuda tensors."""
         n = x.shape[1]
-        arr = (_lib.Scene * len(scenes))()
-        for i, s in enumerate(scenes):
-            arr[i].offset = int(s["offset"])
-            arr[i].count = int(s["count"])
-            arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
-            arr[i].mu = float(s.get("mu", 0.0))
-            arr[i].n_iter = int(s.get("n_iter", 0))
-            arr[i].n_bodies = int(s["n_bodies"])
+        arr = scene_table(scenes)
         keys = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
         perm = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
         rc = lib().apic_sort_keys(self._h, _stream(), arr, len(scenes), n, _ptr(x), _ptr(body),
@@ -167,15 +159,77 @@ class Context:
 
 
 def scene_table(scenes):
+    """The ABI scene table of a list of dicts: offset, count, h, n_bodies and
+    optionally origin, dims, mu, n_iter, flags (PIC | RULE_SEPARATE), accel
+    (the resident driver's mechanical acceleration) and x_ref (reference
+    point of the reported L; default the grid origin)."""
     arr = (_lib.Scene * len(scenes))()
     for i, s in enumerate(scenes):
+        origin = s.get("origin", (0, 0, 0))
         arr[i].offset = int(s["offset"])
         arr[i].count = int(s["count"])
-        arr[i].grid = make_grid(s["h"], s.get("origin", (0, 0, 0)), s.get("dims", (0, 0, 0)))
+        arr[i].grid = make_grid(s["h"], origin, s.get("dims", (0, 0, 0)))
         arr[i].mu = float(s.get("mu", 0.0))
         arr[i].n_iter = int(s.get("n_iter", 0))
         arr[i].n_bodies = int(s["n_bodies"])
+        arr[i].flags = int(s.get("flags", 0))
+        arr[i].reserved = 0
+        arr[i].accel[:] = [float(a) for a in s.get("accel", (0.0, 0.0, 0.0))]
+        arr[i].x_ref[:] = [float(a) for a in s.get("x_ref", origin)]
     return arr
+
+
+class Plan:
+    """A planned contact step (apic_plan_*): the batch is measured once, then
+    step() only enqueues on the current stream (no host synchronisation), so
+    it can be captured into a CUDA/HIP graph."""
+
+    def __init__(self, ctx: Context, scenes, x, body, headroom: float = 1.5):
+        self.n = x.shape[1]
+        self.ns = len(scenes)
+        self.dtype = x.dtype
+        self._ctx = ctx
+        self._h = ctypes.c_void_p()
+        arr = scene_table(scenes)
+        check(lib().apic_plan_create(ctx._h, _stream(), arr, self.ns, self.n, _ptr(x), _ptr(body),
+                                     precision_of(x), float(headroom), ctypes.byref(self._h)),
+              "apic_plan_create")
+
+    def step(self, x, v, C, m, body, normals=None, scenes_dev=None, reports_dev=None,
+             status_dev=None):
+        """Enqueue one step.  scenes_dev: optional uint8 device tensor holding
+        an ABI scene table; reports_dev: optional uint8 device tensor of
+        n_scenes reports; status_dev: optional int32 device tensor."""
+        if _check_tensors(x, v, C, m, body) != self.n or x.dtype != self.dtype:
+            raise ValueError("tensors do not match the plan")
+        check(lib().apic_plan_step(self._h, _stream(), _ptr(scenes_dev), _ptr(x), _ptr(v),
+                                   _ptr(C), _ptr(m), _ptr(body), _ptr(normals),
+                                   _ptr(reports_dev), _ptr(status_dev)), "apic_plan_step")
+
+    def close(self):
+        if self._h:
+            lib().apic_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reports_from_bytes(buf, ns):
+    """Report dicts from the bytes of n_scenes device reports (a uint8 CPU
+    tensor or bytes)."""
+    raw = bytes(buf.numpy().tobytes() if hasattr(buf, "numpy") else buf)
+    arr = (_lib.Report * ns).from_buffer_copy(raw[:ctypes.sizeof(_lib.Report) * ns])
+    return [_lib.report_dict(r) for r in arr]
+
+
+def scene_table_bytes(scenes) -> bytes:
+    """The ABI scene table as bytes (to upload as a device table)."""
+    arr = scene_table(scenes)
+    return bytes(memoryview(arr).cast("B"))
 
 
 class Sim:
@@ -246,8 +300,10 @@ class Sim:
             pass
 
 
-def footprint(n: int, blocks_hint: int = 0, precision: int = _lib.FP32_MIXED) -> int:
-    return int(lib().apic_scene_footprint(int(n), int(blocks_hint), int(precision)))
+def footprint(n: int, h: float = 1.0, origin=(0.0, 0.0, 0.0), dims=(0, 0, 0),
+              precision: int = _lib.FP32_MIXED) -> int:
+    g = make_grid(h, origin, dims)
+    return int(lib().apic_scene_footprint(int(n), ctypes.byref(g), int(precision)))
 
 
 class Server:
@@ -266,6 +322,8 @@ class Server:
                                        int(budget_bytes), ctypes.byref(self._h)),
               "apic_server_create")
         self._done = (ctypes.c_int64 * 4096)()
+        self._status = (ctypes.c_int32 * 4096)()
+        self.failed = {}  # tag -> status of requests retired with an error
 
     def submit(self, tag: int, scene: dict, dt: float, steps: int, x, v, C, m, body,
                x_out, v_out, C_out):
@@ -284,16 +342,27 @@ class Server:
         self._keep[int(tag)] = (x, v, C, m, body, x_out, v_out, C_out)
 
     def tick(self):
-        """One tick; returns (info dict, [completed tags])."""
+        """One tick; returns (info dict, [completed tags]).  Requests retired
+        with an error are recorded in self.failed (tag -> status)."""
         t = _lib.Tick()
         check(lib().apic_server_tick(self._h, _stream(), ctypes.byref(t), self._done,
-                                     len(self._done)), "apic_server_tick")
-        done = [int(self._done[i]) for i in range(min(t.completed, len(self._done)))]
-        for tag in done:
+                                     self._status, len(self._done)), "apic_server_tick")
+        done = []
+        for i in range(min(t.completed + t.failed, len(self._done))):
+            tag, st = int(self._done[i]), int(self._status[i])
             self._keep.pop(tag, None)
+            if st == _lib.OK:
+                done.append(tag)
+            else:
+                self.failed[tag] = st
         info = {"resident": t.resident, "admitted": t.admitted, "completed": t.completed,
-                "queued": t.queued, "particles": t.particles, "footprint": t.footprint}
+                "queued": t.queued, "deferred": t.deferred, "failed": t.failed,
+                "particles": t.particles, "footprint": t.footprint}
         return info, done
+
+    def cancel(self, tag: int):
+        check(lib().apic_server_cancel(self._h, int(tag)), "apic_server_cancel")
+        self._keep.pop(int(tag), None)
 
     def close(self):
         if self._h:

@@ -145,6 +145,10 @@ apic_status validate_scenes(const apic_scene *scenes, int32_t ns, int64_t n_tota
     if (!(sc.mu >= 0.0) || std::isnan(sc.mu)) return APIC_E_INVALID;
     if (sc.n_iter < 0 || sc.n_iter > 64) return APIC_E_INVALID;
     if (sc.n_bodies < 1 || sc.n_bodies > 65536) return APIC_E_INVALID;
+    if ((sc.flags & ~(APIC_PIC | APIC_RULE_SEPARATE)) != 0 || sc.reserved != 0)
+      return APIC_E_INVALID;
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(sc.accel[d]) || !std::isfinite(sc.x_ref[d])) return APIC_E_INVALID;
     bodies += sc.n_bodies;
   }
   if (expect != n_total) return APIC_E_INVALID;
@@ -181,6 +185,11 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
     d.h = scenes[s].grid.h;
     d.mu = scenes[s].mu;
     d.dt = dt ? dt[s] : 0.0;
+    for (int k = 0; k < 3; ++k) {
+      d.accel[k] = scenes[s].accel[k];
+      d.x_ref[k] = scenes[s].x_ref[k];
+    }
+    d.flags = scenes[s].flags;
     d.offset = scenes[s].offset;
     d.count = scenes[s].count;
     d.n_iter = scenes[s].n_iter;
@@ -201,6 +210,8 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
   TRY(W.ensure(kTot, sizeof(int64_t) * 16));
   TRY(W.ensure(kRedBuf, sizeof(double) * kRed * 2 * ns));
   TRY(W.ensure(kBoxRec, sizeof(BoxRec) * std::max<int64_t>(wave_records(n), 1)));
+  TRY(W.ensure(kSceneErr, sizeof(int32_t) * ns));
+  P.scene_err = (int32_t *)W.ptr[kSceneErr];
   P.box_rec = (BoxRec *)W.ptr[kBoxRec];
   P.sc = (SceneDev *)W.ptr[kScenes];
   P.sacc = (SceneAcc *)W.ptr[kSceneAcc];
@@ -308,6 +319,12 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
   TRY(W.ensure(kBMass, T * kNodesPerBlock * P.bblk_cap));
   TRY(W.ensure(kRecGather, sizeof(RedRec) * std::max<int64_t>(wave_records(n), 1)));
   TRY(W.ensure(kRecItems, sizeof(RedRec) * P.item_cap));  // one per work item
+  TRY(W.ensure(kB2S, sizeof(int32_t) * P.bblk_cap));
+  TRY(W.ensure(kNodeCount, sizeof(int32_t) * kNodesPerBlock * P.sblk_cap));
+  TRY(W.ensure(kBodyMax, sizeof(int32_t) * P.ns));
+  P.b2s = (int32_t *)W.ptr[kB2S];
+  P.node_count = (int32_t *)W.ptr[kNodeCount];
+  P.body_max = (int32_t *)W.ptr[kBodyMax];
   P.rec_gather = (RedRec *)W.ptr[kRecGather];
   P.rec_items = (RedRec *)W.ptr[kRecItems];
   P.ka = (uint32_t *)W.ptr[kKeysA];
@@ -350,13 +367,18 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
 // ---------------------------------------------------------------------------
 // enqueue helpers (no host synchronisation inside)
 // ---------------------------------------------------------------------------
+// table_in (device, ABI layout) and plan_sc: a planned step's scene table,
+// checked against the plan's and converted into P.sc before the layout.
 template <typename T>
 static void enqueue_prefix(Plan &P, hipStream_t st, const T *x, const uint16_t *body,
-                           const int32_t *sticky, bool check_caps) {
+                           const int32_t *sticky, bool check_caps,
+                           const apic_scene *table_in = nullptr,
+                           const SceneDev *plan_sc = nullptr) {
   launch_layout_init(P.sacc, P.ns, P.bacc, (int)P.nb_cap, P.cnt, sticky, P.red,
-                     (int64_t)kRed * 2 * P.ns, st);
-  launch_cells<T>(x, body, P.n, P.sc, P.ns, P.bacc, P.box_rec, P.cnt, st);
-  launch_reduce_box(P.box_rec, wave_records(P.n), P.bacc, st);
+                     (int64_t)kRed * 2 * P.ns, P.scene_err, st);
+  if (table_in) launch_scene_table(table_in, plan_sc, P.ns, P.max_iter, P.sc, P.cnt, st);
+  launch_cells<T>(x, body, P.n, P.sc, P.ns, P.bacc, P.box_rec, P.cnt, P.scene_err, st);
+  launch_reduce_box(P.box_rec, wave_records(P.n), P.bacc, P.cnt, st);
   launch_domains(P.sc, P.ns, (int)P.nb_cap, P.sacc, P.bacc, P.slay, P.blay, P.cnt,
                  check_caps ? P.sort_bits : 0, check_caps ? P.smap_cap : 0,
                  check_caps ? P.bmap_cap : 0, st);
@@ -387,7 +409,8 @@ template <typename T>
 static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const T *C, const T *m,
                          const uint16_t *body, T *vbar, T *x_sorted, uint16_t *body_sorted,
                          T *m_sorted, const uint32_t *orig_in, uint32_t *orig_out,
-                         T *v_out, T *C_out, bool unpermute, Profiler *prof) {
+                         T *v_out, T *C_out, bool unpermute, Profiler *prof,
+                         const T *normals = nullptr) {
   const int64_t n = P.n;
   if (prof) prof->begin(st);
   // the gather also orders each wave's particles by cell within a block, and
@@ -396,7 +419,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   uint32_t *perm2 = P.perm == P.va ? P.vb : P.va;
   launch_gather<T>(P.perm, P.keys, n, x, v, C, m, body, P.sc, P.ns, (T *)P.t, vbar, m_sorted,
                    P.sbody, x_sorted, body_sorted, orig_in, orig_out, keys2, perm2, P.rec_gather,
-                   P.red, st);
+                   P.red, normals, (T *)P.nrm, P.cnt, P.scene_err, st);
   P.keys = keys2;
   P.perm = perm2;
   if (prof) prof->end(APIC_KC_GATHER, st), prof->begin(st);
@@ -404,7 +427,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
                   P.item_cap, P.smark, P.smap_cap, P.bmark, P.bmap_cap, P.group, P.cnt, st);
   launch_maps(P.seg, P.seg_cap, P.slay, P.blay, P.smark, P.smap, P.smap_cap, P.bmark, P.bmap,
               P.bmap_cap, P.lb, P.tot, P.cnt, P.sblk_cap, P.bblk_cap, P.item_cap, P.g,
-              (int)P.tbytes, P.node_wg, P.rec_gather, wave_records(n), P.red, st);
+              (int)P.tbytes, P.node_wg, P.rec_gather, wave_records(n), P.red, P.b2s, st);
   StepArgs a;
   a.sc = P.sc;
   a.seg = P.seg;
@@ -417,6 +440,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.xcd_split = P.xcd_split;
   a.item_wg = P.item_wg;
   a.group = P.group;
+  a.given_normals = normals != nullptr ? 1 : 0;
   if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
@@ -441,7 +465,8 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   if (prof) prof->end(APIC_KC_AFTER, st);
 }
 
-static void fill_report(const double *r, int ns, const Counters &c, apic_report *reports) {
+static void fill_report(const double *r, int ns, const Counters &c, apic_report *reports,
+                        const int32_t *body_max = nullptr) {
   for (int s = 0; s < ns; ++s) {
     apic_report &R = reports[s];
     const double *b = r + kRed * s, *af = r + kRed * (ns + s);
@@ -458,7 +483,15 @@ static void fill_report(const double *r, int ns, const Counters &c, apic_report 
     R.n_particles = (int64_t)llround(b[9]);
     R.n_unconstrained = (int64_t)llround(af[10]);
     R.grid_blocks = c.n_sblocks;
+    R.max_bodies_per_node = body_max ? body_max[s] : 0;
+    R.reserved = 0;
   }
+}
+
+template <typename T>
+static void enqueue_bodies_per_node(const Plan &P, hipStream_t st) {
+  launch_bodies_per_node<T>(P.cnt, P.seg, P.seg_cap, (const T *)P.g.bmass, P.b2s, P.bblk_cap,
+                            P.sblk_cap, P.node_count, P.body_max, P.ns, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,43 +503,70 @@ static void fill_report(const double *r, int ns, const Counters &c, apic_report 
 template <typename T>
 static apic_status step_impl(apic_ctx *ctx, Workspace &W, hipStream_t st,
                              const apic_scene *scenes, int32_t ns, int64_t n, const T *x, T *v,
-                             T *C, const T *m, const uint16_t *body, apic_report *reports) {
+                             T *C, const T *m, const uint16_t *body, apic_report *reports,
+                             const T *normals = nullptr, int32_t *scene_err = nullptr,
+                             const double *dt = nullptr) {
   Plan P;
-  TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED,
-                  nullptr, st));
+  TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED, dt,
+                  st));
+  if (scene_err) std::fill(scene_err, scene_err + ns, 0);
   if (n == 0) {
     if (reports)
       for (int s = 0; s < ns; ++s) std::memset(&reports[s], 0, sizeof(apic_report));
     return APIC_OK;
   }
+  // on a device-detected error: the failing scenes' error bits, if asked for
+  auto attribute = [&](apic_status rc) -> apic_status {
+    if (rc != APIC_OK && scene_err && !W.arena) {
+      apic_status r2 = ctx->host_stage(sizeof(int32_t) * ns);
+      if (r2 == APIC_OK && hipMemcpyAsync(ctx->stage, P.scene_err, sizeof(int32_t) * ns,
+                                          hipMemcpyDeviceToHost, st) == hipSuccess &&
+          hipStreamSynchronize(st) == hipSuccess)
+        std::memcpy(scene_err, ctx->stage, sizeof(int32_t) * ns);
+      else
+        (void)hipGetLastError();
+    }
+    return rc;
+  };
   enqueue_prefix<T>(P, st, x, body, nullptr, false);
   Counters c;
   TRY(read_back(ctx, W, &c, P.cnt, sizeof(Counters), st));
-  TRY(status_from_err(c.err));
+  TRY(attribute(status_from_err(c.err)));
   TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0, st));
   TRY(W.ensure(kVbar, sizeof(T) * 12 * n));
   enqueue_sort<T>(P, st, x, body, nullptr);
   enqueue_body<T>(P, st, x, v, C, m, body, (T *)W.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
-                  nullptr, nullptr, v, C, true, nullptr);
+                  nullptr, nullptr, v, C, true, nullptr, normals);
+  if (reports) enqueue_bodies_per_node<T>(P, st);
   if (W.arena) {  // one scene: the sums and counters on the stack
     double red[kRed * 2];
+    int32_t bmax = 0;
     TRY(read_back(ctx, W, red, P.red, sizeof(red), st));
     TRY(read_back(ctx, W, &c, P.cnt, sizeof(Counters), st));
+    if (reports) TRY(read_back(ctx, W, &bmax, P.body_max, sizeof(int32_t), st));
     TRY(status_from_err(c.err));
     if (c.err) return APIC_E_DEVICE;
-    if (reports) fill_report(red, 1, c, reports);
+    if (reports) fill_report(red, 1, c, reports, &bmax);
     return APIC_OK;
   }
   const size_t rbytes = sizeof(double) * kRed * 2 * ns;
-  TRY(ctx->host_stage(rbytes + sizeof(Counters)));
-  HIPOK(hipMemcpyAsync(ctx->stage, P.red, rbytes, hipMemcpyDeviceToHost, st));
-  HIPOK(hipMemcpyAsync((char *)ctx->stage + rbytes, P.cnt, sizeof(Counters),
-                       hipMemcpyDeviceToHost, st));
+  const size_t bbytes = reports ? sizeof(int32_t) * ns : 0;
+  TRY(ctx->host_stage(rbytes + sizeof(Counters) + bbytes));
+  char *stg = (char *)ctx->stage;
+  HIPOK(hipMemcpyAsync(stg, P.red, rbytes, hipMemcpyDeviceToHost, st));
+  HIPOK(hipMemcpyAsync(stg + rbytes, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  if (bbytes)
+    HIPOK(hipMemcpyAsync(stg + rbytes + sizeof(Counters), P.body_max, bbytes,
+                         hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
-  std::memcpy(&c, (char *)ctx->stage + rbytes, sizeof(Counters));
-  TRY(status_from_err(c.err));
+  std::memcpy(&c, stg + rbytes, sizeof(Counters));
+  TRY(attribute(status_from_err(c.err)));
   if (c.err) return APIC_E_DEVICE;
-  if (reports) fill_report((const double *)ctx->stage, ns, c, reports);
+  if (reports) {
+    std::vector<int32_t> bmax(ns);
+    std::memcpy(bmax.data(), stg + rbytes + sizeof(Counters), bbytes);
+    fill_report((const double *)stg, ns, c, reports, bmax.data());
+  }
   return APIC_OK;
 }
 
@@ -673,6 +733,33 @@ static apic_status sim_step_impl(apic_sim *S, hipStream_t st, int32_t n_steps, i
 }
 
 // ---------------------------------------------------------------------------
+// planned (asynchronous) step
+// ---------------------------------------------------------------------------
+struct apic_plan {
+  apic_ctx *ctx = nullptr;
+  Workspace ws;
+  Plan plan;
+  SceneDev *sc_plan = nullptr;  // the scene table the plan was sized for (device)
+  apic_scene *abi = nullptr;    // the same table in the ABI's layout (device)
+};
+
+template <typename T>
+static void enqueue_plan_step(apic_plan *PL, hipStream_t st, const apic_scene *table,
+                              const T *x, T *v, T *C, const T *m, const uint16_t *body,
+                              const T *normals, apic_report *reports, int32_t *status) {
+  Plan &P = PL->plan;
+  enqueue_prefix<T>(P, st, x, body, nullptr, true, table ? table : PL->abi, PL->sc_plan);
+  enqueue_sort<T>(P, st, x, body, nullptr);
+  enqueue_body<T>(P, st, x, v, C, m, body, (T *)PL->ws.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
+                  nullptr, nullptr, v, C, true, nullptr, normals);
+  if (reports) {
+    enqueue_bodies_per_node<T>(P, st);
+    launch_fill_reports(P.red, P.cnt, P.body_max, P.ns, reports, st);
+  }
+  if (status) launch_status(P.cnt, status, st);
+}
+
+// ---------------------------------------------------------------------------
 // scratch of the allocation-free entry point
 // ---------------------------------------------------------------------------
 // A fixed device region (every GPU the library runs on holds its own copy
@@ -706,6 +793,29 @@ static apic_status scratch_address(int device, void **out) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+apic_status contact_step_attributed(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                                    int32_t n_scenes, int64_t n_total, const void *x, void *v,
+                                    void *C, const void *m, const uint16_t *body_id,
+                                    apic_precision prec, const double *dt, int32_t *scene_err) {
+  if (!ctx) return APIC_E_INVALID;
+  TRY(validate_scenes(scenes, n_scenes, n_total));
+  if (n_total > 0 && (!x || !v || !C || !m || !body_id)) return APIC_E_INVALID;
+  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == APIC_FP64)
+    return step_impl<double>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const double *)x,
+                             (double *)v, (double *)C, (const double *)m, body_id, nullptr,
+                             nullptr, scene_err, dt);
+  return step_impl<float>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const float *)x,
+                          (float *)v, (float *)C, (const float *)m, body_id, nullptr, nullptr,
+                          scene_err, dt);
+}
+
+apic_status status_of_error_bits(int32_t err) {
+  apic_status s = status_from_err(err);
+  return s != APIC_OK ? s : (err ? APIC_E_DEVICE : APIC_OK);
+}
+
 extern "C" {
 
 apic_status apic_create(apic_ctx **out, int device, size_t hbm_budget_bytes) {
@@ -757,6 +867,8 @@ const char *apic_status_string(apic_status s) {
     case APIC_E_BODY: return "body id out of range";
     case APIC_E_SCRATCH:
       return "scene needs more than the allocation-free entry point's fixed scratch";
+    case APIC_E_RESIZE: return "planned step outgrew its plan (create a new plan)";
+    case APIC_E_TABLE: return "device scene table does not match its plan";
   }
   return "unknown status";
 }
@@ -764,7 +876,8 @@ const char *apic_status_string(apic_status s) {
 apic_status apic_contact_step_batched(apic_ctx *ctx, void *stream, const apic_scene *scenes,
                                       int32_t n_scenes, int64_t n_total, const void *x, void *v,
                                       void *C, const void *m, const uint16_t *body_id,
-                                      apic_precision prec, apic_report *per_scene) {
+                                      const void *normals, apic_precision prec,
+                                      apic_report *per_scene) {
   if (!ctx) return APIC_E_INVALID;
   TRY(validate_scenes(scenes, n_scenes, n_total));
   if (n_total > 0 && (!x || !v || !C || !m || !body_id)) return APIC_E_INVALID;
@@ -773,9 +886,25 @@ apic_status apic_contact_step_batched(apic_ctx *ctx, void *stream, const apic_sc
   hipStream_t st = (hipStream_t)stream;
   if (prec == APIC_FP64)
     return step_impl<double>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const double *)x,
-                             (double *)v, (double *)C, (const double *)m, body_id, per_scene);
+                             (double *)v, (double *)C, (const double *)m, body_id, per_scene,
+                             (const double *)normals);
   return step_impl<float>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const float *)x,
-                          (float *)v, (float *)C, (const float *)m, body_id, per_scene);
+                          (float *)v, (float *)C, (const float *)m, body_id, per_scene,
+                          (const float *)normals);
+}
+
+// The scene of a single-scene call: any body id below 65536, L about the
+// grid origin, APIC transfers with the Coulomb rule.
+static apic_scene single_scene(const apic_grid *grid, int64_t n, double mu, int32_t n_iter) {
+  apic_scene s{};
+  s.offset = 0;
+  s.count = n;
+  s.grid = *grid;
+  s.mu = mu;
+  s.n_iter = n_iter;
+  s.n_bodies = 65536;
+  for (int d = 0; d < 3; ++d) s.x_ref[d] = grid->origin[d];
+  return s;
 }
 
 apic_status apic_contact_step(apic_ctx *ctx, void *stream, const apic_grid *grid, int64_t n,
@@ -783,14 +912,9 @@ apic_status apic_contact_step(apic_ctx *ctx, void *stream, const apic_grid *grid
                               const uint16_t *body_id, double mu, int32_t n_iter,
                               apic_precision prec, apic_report *report) {
   if (!ctx || !grid) return APIC_E_INVALID;
-  apic_scene s;
-  s.offset = 0;
-  s.count = n;
-  s.grid = *grid;
-  s.mu = mu;
-  s.n_iter = n_iter;
-  s.n_bodies = 65536;
-  return apic_contact_step_batched(ctx, stream, &s, 1, n, x, v, C, m, body_id, prec, report);
+  const apic_scene s = single_scene(grid, n, mu, n_iter);
+  return apic_contact_step_batched(ctx, stream, &s, 1, n, x, v, C, m, body_id, nullptr, prec,
+                                   report);
 }
 
 apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_grid *grid,
@@ -798,13 +922,7 @@ apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_gr
                                       const uint16_t *body_id, double mu, int32_t n_iter,
                                       apic_precision prec, apic_report *report) {
   if (!ctx || !grid) return APIC_E_INVALID;
-  apic_scene s;
-  s.offset = 0;
-  s.count = n;
-  s.grid = *grid;
-  s.mu = mu;
-  s.n_iter = n_iter;
-  s.n_bodies = 65536;
+  const apic_scene s = single_scene(grid, n, mu, n_iter);
   TRY(validate_scenes(&s, 1, n));
   if (n > 0 && (!x || !v || !C || !m || !body_id)) return APIC_E_INVALID;
   if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
@@ -823,6 +941,82 @@ apic_status apic_contact_step_noalloc(apic_ctx *ctx, void *stream, const apic_gr
                              (double *)C, (const double *)m, body_id, report);
   return step_impl<float>(ctx, W, st, &s, 1, n, (const float *)x, (float *)v, (float *)C,
                           (const float *)m, body_id, report);
+}
+
+apic_status apic_plan_create(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                             int32_t n_scenes, int64_t n_total, const void *x,
+                             const uint16_t *body_id, apic_precision prec, double headroom,
+                             apic_plan **out) {
+  if (!ctx || !out) return APIC_E_INVALID;
+  *out = nullptr;
+  TRY(validate_scenes(scenes, n_scenes, n_total));
+  if (n_total < 1 || !x || !body_id) return APIC_E_INVALID;
+  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
+  if (!(headroom >= 1.0) || !(headroom <= 64.0)) return APIC_E_INVALID;
+  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  apic_plan *PL = new apic_plan();
+  PL->ctx = ctx;
+  PL->ws.budget = ctx->ws.budget;
+  auto fail = [&](apic_status rc) {
+    apic_plan_destroy(PL);
+    return rc;
+  };
+  Plan &P = PL->plan;
+  apic_status rc = plan_tables(ctx, PL->ws, P, scenes, n_scenes, n_total, prec, nullptr, st);
+  if (rc) return fail(rc);
+  const size_t sbytes = sizeof(SceneDev) * n_scenes, abytes = sizeof(apic_scene) * n_scenes;
+  if ((rc = PL->ws.ensure(kPlanSc, sbytes)) || (rc = PL->ws.ensure(kPlanAbi, abytes)))
+    return fail(rc);
+  PL->sc_plan = (SceneDev *)PL->ws.ptr[kPlanSc];
+  PL->abi = (apic_scene *)PL->ws.ptr[kPlanAbi];
+  if ((rc = ctx->host_stage(abytes))) return fail(rc);
+  std::memcpy(ctx->stage, scenes, abytes);
+  if (hipMemcpyAsync(PL->sc_plan, P.sc, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(PL->abi, ctx->stage, abytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(APIC_E_DEVICE);
+  }
+  if (prec == APIC_FP64)
+    enqueue_prefix<double>(P, st, (const double *)x, body_id, nullptr, false);
+  else
+    enqueue_prefix<float>(P, st, (const float *)x, body_id, nullptr, false);
+  Counters c;
+  if ((rc = read_back(ctx, PL->ws, &c, P.cnt, sizeof(Counters), st))) return fail(rc);
+  if ((rc = status_from_err(c.err))) return fail(rc);
+  if ((rc = plan_buffers(ctx, PL->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom,
+                         st)))
+    return fail(rc);
+  if ((rc = PL->ws.ensure(kVbar, (size_t)P.tbytes * 12 * n_total))) return fail(rc);
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(APIC_E_DEVICE);
+  *out = PL;
+  return APIC_OK;
+}
+
+apic_status apic_plan_step(apic_plan *PL, void *stream, const apic_scene *scenes_dev,
+                           const void *x, void *v, void *C, const void *m,
+                           const uint16_t *body_id, const void *normals,
+                           apic_report *reports_dev, int32_t *status_dev) {
+  if (!PL || !x || !v || !C || !m || !body_id) return APIC_E_INVALID;
+  if (hipSetDevice(PL->ctx->device) != hipSuccess) return APIC_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (PL->plan.prec == APIC_FP64)
+    enqueue_plan_step<double>(PL, st, scenes_dev, (const double *)x, (double *)v, (double *)C,
+                              (const double *)m, body_id, (const double *)normals, reports_dev,
+                              status_dev);
+  else
+    enqueue_plan_step<float>(PL, st, scenes_dev, (const float *)x, (float *)v, (float *)C,
+                             (const float *)m, body_id, (const float *)normals, reports_dev,
+                             status_dev);
+  return APIC_OK;
+}
+
+void apic_plan_destroy(apic_plan *PL) {
+  if (!PL) return;
+  (void)hipSetDevice(PL->ctx->device);
+  (void)hipDeviceSynchronize();
+  PL->ws.release();
+  delete PL;
 }
 
 apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes,
@@ -861,10 +1055,18 @@ apic_status apic_sort_keys(apic_ctx *ctx, void *stream, const apic_scene *scenes
   return APIC_OK;
 }
 
-int64_t apic_scene_footprint(int64_t n, int64_t blocks_hint, apic_precision prec) {
+int64_t apic_scene_footprint(int64_t n, const apic_grid *grid, apic_precision prec) {
   if (n < 0) return -1;
   const int64_t tb = prec == APIC_FP64 ? 8 : 4;
-  if (blocks_hint <= 0) blocks_hint = n / 16 + 64;
+  // node blocks: about one per 16 particles plus a margin (lattice solids
+  // touch about 1.3-2 node blocks per 64 particles, small scenes more), at
+  // most what a dense grid holds
+  int64_t blocks_hint = n / 16 + 64;
+  if (grid && grid->dims[0] > 0 && grid->dims[1] > 0 && grid->dims[2] > 0) {
+    int64_t dense = 1;
+    for (int d = 0; d < 3; ++d) dense *= (int64_t)grid->dims[d] / kBlock + 2;
+    blocks_hint = std::min(blocks_hint, dense);
+  }
   // resident state x2 (x, vC, m, body, orig), sorted scratch (t, m, normals,
   // series), keys/values x2; work items and their reduction records (one per
   // 64 particles plus about two per block), one segment per block; grid mass,
@@ -969,15 +1171,28 @@ apic_status apic_sim_report(apic_sim *S, apic_report *per_scene, double *max_dri
   if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
   const int ns = S->n_scenes;
   const size_t rbytes = sizeof(double) * kRed * 2 * ns;
-  TRY(S->ctx->host_stage(rbytes + sizeof(Counters) + sizeof(double) * 2 * ns));
+  const size_t dbytes = sizeof(double) * 2 * ns, bbytes = sizeof(int32_t) * ns;
+  TRY(S->ctx->host_stage(rbytes + sizeof(Counters) + dbytes + bbytes));
   char *stg = (char *)S->ctx->stage;
+  // the last step's grids are still in place: count bodies per node from them
+  if (per_scene && S->steps_done > 0) {
+    if (S->plan.prec == APIC_FP64)
+      enqueue_bodies_per_node<double>(S->plan, nullptr);
+    else
+      enqueue_bodies_per_node<float>(S->plan, nullptr);
+  }
   HIPOK(hipMemcpy(stg, S->plan.red, rbytes, hipMemcpyDeviceToHost));
   HIPOK(hipMemcpy(stg + rbytes, S->plan.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
-  HIPOK(hipMemcpy(stg + rbytes + sizeof(Counters), S->drift, sizeof(double) * 2 * ns,
+  HIPOK(hipMemcpy(stg + rbytes + sizeof(Counters), S->drift, dbytes, hipMemcpyDeviceToHost));
+  HIPOK(hipMemcpy(stg + rbytes + sizeof(Counters) + dbytes, S->plan.body_max, bbytes,
                   hipMemcpyDeviceToHost));
   Counters c;
   std::memcpy(&c, stg + rbytes, sizeof(Counters));
-  if (per_scene) fill_report((const double *)stg, ns, c, per_scene);
+  if (per_scene) {
+    std::vector<int32_t> bmax(ns, 0);
+    if (S->steps_done > 0) std::memcpy(bmax.data(), stg + rbytes + sizeof(Counters) + dbytes, bbytes);
+    fill_report((const double *)stg, ns, c, per_scene, bmax.data());
+  }
   if (max_drift) std::memcpy(max_drift, stg + rbytes + sizeof(Counters), sizeof(double) * 2 * ns);
   if (steps_done) *steps_done = S->steps_done;
   return APIC_OK;

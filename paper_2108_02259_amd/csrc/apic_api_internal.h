@@ -32,7 +32,8 @@ enum BufId {
   kScenes, kSceneAcc, kSceneLay, kBodyAcc, kBodyLay, kCounters, kTot, kKeysA, kValsA, kKeysB,
   kValsB, kGhist, kLbFlags, kLbState, kT, kVbar, kMs, kSbody, kNrm, kY, kRedBuf, kSeg,
   kItems, kSmark, kSmap, kBmark, kBmap, kGMass, kGBuf0, kGBuf1, kGBuf2, kInvM, kBMass,
-  kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kNumBufs
+  kBoxRec, kRecGather, kRecItems, kTuneV, kTuneC, kB2S, kNodeCount, kBodyMax, kPlanSc,
+  kPlanAbi, kSceneErr, kNumBufs
 };
 
 // Grow-only device buffers, bounded by an HBM budget.  In arena mode (arena
@@ -87,6 +88,11 @@ struct Plan {
   Segment *seg = nullptr;
   Item *items = nullptr;
   int32_t *smark = nullptr, *smap = nullptr, *bmark = nullptr, *bmap = nullptr;
+  int32_t *b2s = nullptr;         // body-grid block -> shared-grid block
+  int32_t *node_count = nullptr;  // bodies with mass per shared node (reports)
+  int32_t *body_max = nullptr;    // per scene: most bodies at one node
+  int32_t *scene_err = nullptr;   // per scene: error bits of its particles
+  bool given_normals = false;
   GridPtrs g = {};
 };
 
@@ -169,3 +175,17 @@ struct apic_sim {
 };
 
 apic_status validate_scenes(const apic_scene *scenes, int32_t ns, int64_t n_total);
+
+// apic_contact_step_batched with the driver's prediction and error
+// attribution: with dt (host, n_scenes entries, may be null) the step's input
+// is Vbar = V + dt {a, 0} with each scene's accel (formed on the device; v
+// itself is only overwritten by the result); when the device detects an
+// error in some scenes' particles (non-finite values, body id, out of a dense
+// grid), *scene_err (host, n_scenes entries) receives each scene's error
+// bits (apic::kErr*), all zero otherwise.  v and C are untouched on error.
+apic_status contact_step_attributed(apic_ctx *ctx, void *stream, const apic_scene *scenes,
+                                    int32_t n_scenes, int64_t n_total, const void *x, void *v,
+                                    void *C, const void *m, const uint16_t *body_id,
+                                    apic_precision prec, const double *dt, int32_t *scene_err);
+// The apic_status an error word maps to.
+apic_status status_of_error_bits(int32_t err);

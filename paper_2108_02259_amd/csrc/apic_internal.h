@@ -50,6 +50,7 @@ enum : int32_t {
   kErrBody = 8,
   kErrNonFinite = 16,
   kErrResize = 32,      // key space or map exceeded a resident plan's capacity
+  kErrTable = 64,       // a device scene table does not match its plan
 };
 
 // ---------------------------------------------------------------------------
@@ -60,11 +61,15 @@ struct SceneDev {
   double h;
   double mu;
   double dt;             // drift step of the resident driver (0 in a single call)
+  double accel[3];       // mechanical acceleration (Vbar = V + dt a; dt = 0 in a single call)
+  double x_ref[3];       // reference point of the reported angular momentum
   int64_t offset, count;
   int32_t dims[3];
   int32_t n_iter;
   int32_t body_base;  // capacity index of this scene's body 0
   int32_t n_bodies;   // body ids must be < n_bodies
+  int32_t flags;      // APIC_PIC | APIC_RULE_SEPARATE
+  int32_t pad;
 };
 
 // Accumulated with atomics while cells are computed.
@@ -127,7 +132,8 @@ struct Counters {
   int32_t n_items;
   int32_t n_sblocks;     // active shared-grid node blocks
   int32_t n_bblocks;     // active body-grid node blocks
-  int32_t pad0, pad1;
+  int32_t max_gb;        // largest capacity body index holding a particle (-1: none)
+  int32_t pad1;
   int64_t smap_total;
   int64_t bmap_total;
 };
@@ -231,8 +237,8 @@ __device__ __forceinline__ double wave_sum_spread(const double (&q)[K]) {
   return v;
 }
 
-// P(3), L(3) about the scene origin with the affine spin, E, P scale, L scale,
-// particle count, unconstrained count (filled elsewhere).
+// P(3), L(3) about the scene's reference point with the affine spin, E, P
+// scale, L scale, particle count, unconstrained count (filled elsewhere).
 __device__ __forceinline__ void momentum_terms(const double r[3], const double v[3],
                                                const double C[9], double m, double h,
                                                double q[kRed]) {

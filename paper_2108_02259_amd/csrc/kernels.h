@@ -78,12 +78,13 @@ struct GridPtrs {
 // One box record per wavefront (rec has ceil(n/256)*4 entries), then reduced.
 template <typename T>
 void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, hipStream_t st);
+                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, int32_t *scene_err, hipStream_t st);
 inline int64_t wave_records(int64_t n) { return (n + 255) / 256 * 4; }
 // Empty boxes, zero counters (error word from sticky if given) and cleared
 // per-scene sums red[0, red_n).
 void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
-                        const int32_t *sticky, double *red, int64_t red_n, hipStream_t st);
+                        const int32_t *sticky, double *red, int64_t red_n, int32_t *scene_err,
+                        hipStream_t st);
 // key_bits > 0: flag kErrResize if the key space needs more bits; smap_cap /
 // bmap_cap > 0: flag kErrResize if the node-block maps need more entries.
 void launch_domains(const SceneDev *sc, int ns, int nb_cap, SceneAcc *sacc, const BodyAcc *bacc,
@@ -104,6 +105,7 @@ void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const 
                    int ns, T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out,
                    T *x_out, uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
                    uint32_t *keys_out, uint32_t *perm_out, RedRec *rec, double *direct,
+                   const T *nrm_in, T *nrm_out, Counters *cnt, int32_t *scene_err,
                    hipStream_t st);
 // Segments (one per (body, cell block) of the sorted keys, with their node
 // blocks marked in smark/bmark) and work items, from two single-pass scans;
@@ -124,7 +126,7 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
                  int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
                  int node_wg, const RedRec *grec, int64_t grec_count, double *gred,
-                 hipStream_t st);
+                 int32_t *b2s, hipStream_t st);
 
 // ---- transfers (transfer.hip) ---------------------------------------------
 
@@ -140,6 +142,7 @@ struct StepArgs {
   int node_wg;           // 256-lane workgroups of the node kernels
   int xcd_split;         // 1: each XCD walks one contiguous eighth of the items
   int group;             // work items merged per workgroup before the flush (1, 4, 8)
+  int given_normals;     // 1: the normals array holds the caller's normals
 };
 
 template <typename T>
@@ -171,7 +174,28 @@ void launch_final(const StepArgs &a, int k, const T *t, const T *m, const T *vba
 // step has an error) into out[key * kRed + c].
 void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *count_dev,
                        const Counters *cnt, double *out, hipStream_t st);
-// Reduce box records into the per-body boxes.
-void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, hipStream_t st);
+// Reduce box records into the per-body boxes (and cnt->max_gb).
+void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, Counters *cnt,
+                       hipStream_t st);
+// Most bodies with mass at one node, per scene, into body_max[scene]: node
+// counts over the body-grid blocks (b2s maps a body block to its shared
+// block), then a maximum over each segment's shared blocks.  count holds
+// sblk_cap * 64 int32.
+template <typename T>
+void launch_bodies_per_node(const Counters *cnt, const Segment *seg, int64_t seg_cap,
+                            const T *bmass, const int32_t *b2s, int64_t bblk_cap,
+                            int64_t sblk_cap, int32_t *count, int32_t *body_max, int ns,
+                            hipStream_t st);
+// Per-scene reports on the device from the step's sums (red: before then
+// after, kRed each per scene), counters and body maxima (may be null).
+void launch_fill_reports(const double *red, const Counters *cnt, const int32_t *body_max, int ns,
+                         apic_report *out, hipStream_t st);
+// The step's status (0 or an apic_status) from the counters' error word.
+void launch_status(const Counters *cnt, int32_t *status, hipStream_t st);
+// Scene table of a planned step: the caller's device table (or the plan's,
+// both in the ABI's layout) checked against the plan's and converted into
+// `out`; a mismatch sets kErrTable.
+void launch_scene_table(const apic_scene *in, const SceneDev *plan_sc, int ns, int max_iter,
+                        SceneDev *out, Counters *cnt, hipStream_t st);
 
 }  // namespace apic

@@ -60,9 +60,11 @@ __device__ __forceinline__ void wave_minmax3(int32_t mn[3], int32_t mx[3]) {
 // error word taken from `sticky` when given), and the per-scene reduction
 // sums cleared (red_n doubles).
 __global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
-                              const int32_t *sticky, double *red, int64_t red_n) {
+                              const int32_t *sticky, double *red, int64_t red_n,
+                              int32_t *scene_err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ns) {
+    scene_err[i] = 0;
     for (int d = 0; d < 3; ++d) {
       sacc[i].bmin[d] = INT_MAX;
       sacc[i].bmax[d] = INT_MIN;
@@ -78,15 +80,17 @@ __global__ void k_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap,
   if (i == 0) {
     Counters z = {};
     if (sticky) z.err = *sticky;
+    z.max_gb = -1;
     *cnt = z;
   }
 }
 
 void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Counters *cnt,
-                        const int32_t *sticky, double *red, int64_t red_n, hipStream_t st) {
+                        const int32_t *sticky, double *red, int64_t red_n, int32_t *scene_err,
+                        hipStream_t st) {
   int64_t m = std::max<int64_t>({(int64_t)ns, (int64_t)nb_cap, red_n, (int64_t)1});
   APIC_LAUNCH(k_layout_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, sacc, ns, bacc,
-              nb_cap, cnt, sticky, red, red_n);
+              nb_cap, cnt, sticky, red, red_n, scene_err);
 }
 
 // Cells of every particle; each wavefront emits one record with the block box
@@ -95,15 +99,15 @@ void launch_layout_init(SceneAcc *sacc, int ns, BodyAcc *bacc, int nb_cap, Count
 template <typename T>
 __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body, int64_t n,
                                                const SceneDev *sc, int ns, BodyAcc *bacc,
-                                               BoxRec *rec, Counters *cnt) {
+                                               BoxRec *rec, Counters *cnt, int32_t *scene_err) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int64_t wave = p >> 6;
   bool ok = p < n;
-  int gb = 0, err = 0;
+  int gb = 0, err = 0, s = 0;
   int32_t B[3] = {0, 0, 0};
   if (ok) {
-    const int s = scene_of(sc, ns, p);
+    s = scene_of(sc, ns, p);
     const SceneDev sd = sc[s];
     CellInfo ci = cell_of(x, n, p, sd);
     err |= ci.err;
@@ -117,7 +121,10 @@ __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body,
 #pragma unroll
     for (int d = 0; d < 3; ++d) B[d] = floor_div4(ci.c[d]);
   }
-  if (err) atomicOr(&cnt->err, err);
+  if (err) {
+    atomicOr(&cnt->err, err);
+    atomicOr(&scene_err[s], err);  // which scene's particles are at fault
+  }
   const uint64_t valid = __ballot(ok);
   BoxRec r;
   r.key = -1;
@@ -146,6 +153,7 @@ __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body,
         atomicMin(&bacc[gb].bmin[d], B[d]);
         atomicMax(&bacc[gb].bmax[d], B[d]);
       }
+      atomicMax(&cnt->max_gb, gb);
     }
   }
   if (lane == 0) rec[wave] = r;
@@ -153,25 +161,31 @@ __global__ __launch_bounds__(256) void k_cells(const T *x, const uint16_t *body,
 
 template <typename T>
 void launch_cells(const T *x, const uint16_t *body, int64_t n, const SceneDev *sc, int ns,
-                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, hipStream_t st) {
+                  BodyAcc *bacc, BoxRec *rec, Counters *cnt, int32_t *scene_err, hipStream_t st) {
   if (n <= 0) return;
-  APIC_LAUNCH((k_cells<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, body, n, sc, ns, bacc, rec, cnt);
+  APIC_LAUNCH((k_cells<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, body, n, sc,
+              ns, bacc, rec, cnt, scene_err);
 }
 
 // Block-wide reduction of 256 box records: one set of atomics per block when
-// all its records name one body, per record otherwise.
+// all its records name one body, per record otherwise; and one atomic max of
+// the block's largest body index into cnt->max_gb.
 __global__ __launch_bounds__(256) void k_reduce_box(const BoxRec *rec, int64_t count,
-                                                    BodyAcc *bacc) {
+                                                    BodyAcc *bacc, Counters *cnt) {
   __shared__ int32_t smn[3][4], smx[3][4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   BoxRec r;
   r.key = -1;
   if (i < count) r = rec[i];
-  __shared__ int32_t key0;
-  if (threadIdx.x == 0) key0 = -2;
+  __shared__ int32_t key0, kmax;
+  if (threadIdx.x == 0) key0 = -2, kmax = -1;
   __syncthreads();
-  if (r.key >= 0) atomicCAS(&key0, -2, r.key);
+  if (r.key >= 0) {
+    atomicCAS(&key0, -2, r.key);
+    atomicMax(&kmax, r.key);
+  }
   __syncthreads();
+  if (threadIdx.x == 0 && kmax >= 0) atomicMax(&cnt->max_gb, kmax);
   const int k0 = key0;
   const bool uniform = __syncthreads_and(r.key < 0 || r.key == k0);
   if (k0 < 0) return;  // no valid record in this block
@@ -208,9 +222,11 @@ __global__ __launch_bounds__(256) void k_reduce_box(const BoxRec *rec, int64_t c
   }
 }
 
-void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, hipStream_t st) {
+void launch_reduce_box(const BoxRec *rec, int64_t count, BodyAcc *bacc, Counters *cnt,
+                       hipStream_t st) {
   if (count <= 0) return;
-  APIC_LAUNCH(k_reduce_box, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, rec, count, bacc);
+  APIC_LAUNCH(k_reduce_box, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, rec, count,
+              bacc, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -258,12 +274,14 @@ __global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, in
                                                   int64_t bmap_cap) {
   __shared__ int64_t lds[16];
   int64_t carry_key = 0, carry_bmap = 0, carry_smap = 0;
-  for (int base = 0; base < nb_cap; base += 1024) {
+  // bodies past the last one holding a particle are empty and never looked up
+  const int nb_used = min(nb_cap, cnt->max_gb + 1);
+  for (int base = 0; base < nb_used; base += 1024) {
     const int gb = base + threadIdx.x;
     int64_t kv = 0, mv = 0;
     BodyAcc ba;
     bool ne = false;
-    if (gb < nb_cap) {
+    if (gb < nb_used) {
       ba = bacc[gb];
       ne = ba.bmin[0] <= ba.bmax[0];
       if (ne) {
@@ -279,7 +297,7 @@ __global__ __launch_bounds__(1024) void k_domains(const SceneDev *sc, int ns, in
     int64_t tk, tb;
     const int64_t koff = block_excl_scan64(kv, lds, &tk) + carry_key;
     const int64_t boff = block_excl_scan64(mv, lds, &tb) + carry_bmap;
-    if (gb < nb_cap) {
+    if (gb < nb_used) {
       const int s = scene_of_body(sc, ns, gb);
       BodyLay bl;
       bl.scene = s;
@@ -473,6 +491,10 @@ __device__ __forceinline__ int64_t cell_order_slot(int64_t i, bool ok, uint32_t 
   return i - lane + start + less + below;
 }
 
+// Also forms the step's input Vbar = V + dt {a, 0} (the resident driver's
+// prediction; dt = 0 in a stateless call), copies the caller's normals into
+// sorted order when given, and flags non-finite velocities, affine matrices
+// or normals and non-positive or non-finite masses.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, const uint32_t *keys,
                                                 int64_t n, const T *x,
@@ -482,13 +504,15 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, const uint
                                                 int32_t *sbody_out, T *x_out, uint16_t *body_out,
                                                 const uint32_t *orig_in, uint32_t *orig_out,
                                                 uint32_t *keys_out, uint32_t *perm_out,
-                                                RedRec *rec, double *direct) {
+                                                RedRec *rec, double *direct, const T *nrm_in,
+                                                T *nrm_out, Counters *cnt, int32_t *scene_err) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i0 < n;
   const uint32_t key = ok ? keys[i0] : 0u;
   const int64_t i = cell_order_slot(i0, ok, key);
   int s = 0;
   double q[kRed];
+  bool bad = false;
   if (ok) {
     const int64_t p = perm[i0];
     keys_out[i] = key;
@@ -498,30 +522,45 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *perm, const uint
     CellInfo ci = cell_of(x, n, p, sd);
 #pragma unroll
     for (int d = 0; d < 3; ++d) t_out[d * n + i] = (T)ci.t[d];
+    const bool accel = sd.dt != 0.0 && (sd.accel[0] != 0.0 || sd.accel[1] != 0.0 ||
+                                        sd.accel[2] != 0.0);
     double vv[3], CC[9], r[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T val = v[d * n + p];
+      if (accel) val = (T)((double)val + sd.dt * sd.accel[d]);
+      bad |= !isfinite((double)val);
       vbar_out[d * n + i] = val;
       vv[d] = (double)val;
       T xv = x[d * n + p];
-      r[d] = (double)xv - sd.origin[d];
+      r[d] = (double)xv - sd.x_ref[d];
       if (x_out) x_out[d * n + i] = xv;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       T val = C[k * n + p];
+      bad |= !isfinite((double)val);
       vbar_out[(3 + k) * n + i] = val;
       CC[k] = (double)val;
     }
     const T mv = m[p];
+    bad |= !(mv > T(0)) || !isfinite((double)mv);
     m_out[i] = mv;
+    if (nrm_in)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T nv = nrm_in[d * n + p];
+        bad |= !isfinite((double)nv);
+        nrm_out[d * n + i] = nv;
+      }
     const int b = body[p];
     sbody_out[i] = sd.body_base + (b < sd.n_bodies ? b : 0);
     if (body_out) body_out[i] = (uint16_t)b;
     if (orig_out) orig_out[i] = orig_in ? orig_in[p] : (uint32_t)p;
     if (rec) momentum_terms(r, vv, CC, (double)mv, sd.h, q);
+    if (bad) atomicOr(&scene_err[s], kErrNonFinite);
   }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&cnt->err, kErrNonFinite);
   if (rec) reduce_scene(ok, s, q, rec, i0 >> 6, direct);
 }
 
@@ -531,11 +570,13 @@ void launch_gather(const uint32_t *perm, const uint32_t *keys, int64_t n, const 
                    T *t_out, T *vbar_out, T *m_out, int32_t *sbody_out, T *x_out,
                    uint16_t *body_out, const uint32_t *orig_in, uint32_t *orig_out,
                    uint32_t *keys_out, uint32_t *perm_out, RedRec *rec, double *direct,
+                   const T *nrm_in, T *nrm_out, Counters *cnt, int32_t *scene_err,
                    hipStream_t st) {
   if (n <= 0) return;
   APIC_LAUNCH((k_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, keys, n,
               x, v, C, m, body, sc, ns, t_out, vbar_out, m_out, sbody_out, x_out, body_out,
-              orig_in, orig_out, keys_out, perm_out, rec, direct);
+              orig_in, orig_out, keys_out, perm_out, rec, direct, nrm_in, nrm_out, cnt,
+              scene_err);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,7 +758,7 @@ __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const 
                             int64_t bmap_cap, const int64_t *tot, int64_t sblk_cap,
                             int64_t bblk_cap, int64_t item_cap, uint32_t *mass, uint32_t *q0,
                             uint32_t *q1, uint32_t *bmass, int words, const RedRec *grec,
-                            int64_t grec_count, double *gred) {
+                            int64_t grec_count, double *gred, int32_t *b2s) {
   // the gather's per-wave momentum records (workgroup-uniform loop)
   for (int64_t rb = blockIdx.x; rb * 256 < grec_count; rb += gridDim.x)
     reduce_rec_block(grec, rb * 256, grec_count, gred);
@@ -746,8 +787,10 @@ __global__ void k_seg_slots(Segment *seg, Counters *cnt, int64_t seg_cap, const 
     int64_t si = smap_index(slay[sg.scene], bx, by, bz);
     int64_t bi = bmap_index(blay[sg.body], bx, by, bz);
     const bool sok = si >= 0 && si < smap_cap, bok = bi >= 0 && bi < bmap_cap;
-    sg.sslot[j] = sok ? smap[si] : -1;
-    sg.bslot[j] = bok ? bmap[bi] : -1;
+    const int32_t ss = sok ? smap[si] : -1, bs = bok ? bmap[bi] : -1;
+    sg.sslot[j] = ss;
+    sg.bslot[j] = bs;
+    if (b2s && bs >= 0 && bs < bblk_cap) b2s[bs] = ss;  // the same node block on the shared grid
     if (sok) smark[si] = 0;
     if (bok) bmark[bi] = 0;
   }
@@ -770,7 +813,7 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
                  int64_t bmap_cap, const Lookback &lb, int64_t *tot, Counters *cnt,
                  int64_t sblk_cap, int64_t bblk_cap, int64_t item_cap, GridPtrs g, int tbytes,
                  int node_wg, const RedRec *grec, int64_t grec_count, double *gred,
-                 hipStream_t st) {
+                 int32_t *b2s, hipStream_t st) {
   int64_t blocks = std::max<int64_t>((seg_cap * 8 + 255) / 256, node_wg);
   if (blocks > 8192) blocks = 8192;
   scan_exclusive_pair(smark, smap, smap_cap, &tot[5], &tot[2], bmark, bmap, bmap_cap, &tot[6],
@@ -778,7 +821,7 @@ void launch_maps(Segment *seg, int64_t seg_cap, const SceneLay *slay, const Body
   APIC_LAUNCH(k_seg_slots, dim3((unsigned)blocks), dim3(256), 0, st, seg, cnt, seg_cap, slay,
               blay, smark, smap, smap_cap, bmark, bmap, bmap_cap, tot, sblk_cap, bblk_cap,
               item_cap, (uint32_t *)g.mass, (uint32_t *)g.buf[0], (uint32_t *)g.buf[1],
-              (uint32_t *)g.bmass, tbytes / 4, grec, grec_count, gred);
+              (uint32_t *)g.bmass, tbytes / 4, grec, grec_count, gred, b2s);
 }
 
 // One workgroup per 256 records (skipped when the step has an error).
@@ -800,9 +843,9 @@ void launch_reduce_red(const RedRec *rec, int64_t count_cap, const int32_t *coun
 
 // explicit instantiations
 template void launch_cells<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
-                                  BodyAcc *, BoxRec *, Counters *, hipStream_t);
+                                  BodyAcc *, BoxRec *, Counters *, int32_t *, hipStream_t);
 template void launch_cells<double>(const double *, const uint16_t *, int64_t, const SceneDev *,
-                                   int, BodyAcc *, BoxRec *, Counters *, hipStream_t);
+                                   int, BodyAcc *, BoxRec *, Counters *, int32_t *, hipStream_t);
 template void launch_keys<float>(const float *, const uint16_t *, int64_t, const SceneDev *, int,
                                  const BodyLay *, uint32_t *, int, uint32_t *, hipStream_t);
 template void launch_keys<double>(const double *, const uint16_t *, int64_t, const SceneDev *, int,
@@ -810,10 +853,10 @@ template void launch_keys<double>(const double *, const uint16_t *, int64_t, con
 template void launch_gather<float>(const uint32_t *, const uint32_t *, int64_t, const float *,
     const float *, const float *, const float *, const uint16_t *, const SceneDev *, int, float *,
     float *, float *, int32_t *, float *, uint16_t *, const uint32_t *, uint32_t *, uint32_t *,
-    uint32_t *, RedRec *, double *, hipStream_t);
+    uint32_t *, RedRec *, double *, const float *, float *, Counters *, int32_t *, hipStream_t);
 template void launch_gather<double>(const uint32_t *, const uint32_t *, int64_t, const double *,
     const double *, const double *, const double *, const uint16_t *, const SceneDev *, int, double *,
     double *, double *, int32_t *, double *, uint16_t *, const uint32_t *, uint32_t *, uint32_t *,
-    uint32_t *, RedRec *, double *, hipStream_t);
+    uint32_t *, RedRec *, double *, const double *, double *, Counters *, int32_t *, hipStream_t);
 
 }  // namespace apic

@@ -89,6 +89,7 @@ struct ServerReq {
   void *xo = nullptr, *vo = nullptr, *Co = nullptr;
   int64_t offset = 0;  // in the arena while resident
   int64_t footprint = 0;
+  bool cancelled = false;
 };
 
 struct apic_server {
@@ -141,10 +142,83 @@ static apic_status copy_segs(apic_server *S, hipStream_t st, const std::vector<C
   return APIC_OK;
 }
 
+// Repack the arena into its other copy: the residents (survivors at their
+// current offsets) then the newcomers (from the caller's arrays), and upload
+// the scene offsets and time steps of the position update.  The copy
+// completes before the next host write of the staging buffer (the tick
+// synchronises before returning).
+template <typename T>
+static apic_status repack(apic_server *S, hipStream_t st, std::vector<ServerReq> &joined) {
+  int64_t n_new = 0;
+  for (const ServerReq &r : S->resident) n_new += r.n;
+  for (const ServerReq &r : joined) n_new += r.n;
+  const int src = S->cur, dst = 1 - S->cur;
+  void *sx, *sv, *sC, *sm, *dx, *dv, *dC, *dm;
+  arena_cols(S, src, S->n_res, &sx, &sv, &sC, &sm);
+  arena_cols(S, dst, n_new, &dx, &dv, &dC, &dm);
+  std::vector<CopySeg> segs;
+  int64_t off = 0;
+  auto add = [&](const void *ax, const void *av, const void *aC, const void *am,
+                 const uint16_t *ab, int64_t s_stride, int64_t s_off, int64_t count) {
+    CopySeg c;
+    c.sx = ax, c.sv = av, c.sC = aC, c.sm = am, c.sb = ab;
+    c.dx = dx, c.dv = dv, c.dC = dC, c.dm = dm, c.db = S->body[dst];
+    c.s_stride = s_stride, c.s_off = s_off, c.d_stride = n_new, c.d_off = off;
+    c.count = count, c.start = off;
+    segs.push_back(c);
+    off += count;
+  };
+  for (ServerReq &r : S->resident) {
+    if (r.n > 0) add(sx, sv, sC, sm, S->body[src], S->n_res, r.offset, r.n);
+    r.offset = off - r.n;
+  }
+  for (ServerReq &r : joined) {
+    if (r.n > 0) add(r.x, r.v, r.C, r.m, r.body, r.n, 0, r.n);
+    r.offset = off - r.n;
+    S->resident.push_back(r);
+  }
+  joined.clear();
+  TRY(copy_segs<T>(S, st, segs, 0));
+  S->cur = dst;
+  S->n_res = n_new;
+  const int ns = (int)S->resident.size();
+  size_t toff = sizeof(CopySeg) * (size_t)(2 * S->max_scenes + 2);
+  int64_t *ho = (int64_t *)((char *)S->stage + toff);
+  double *hd = (double *)((char *)S->stage + toff + sizeof(int64_t) * (S->max_scenes + 1));
+  for (int i = 0; i < ns; ++i) ho[i] = S->resident[i].offset, hd[i] = S->resident[i].dt;
+  if (ns > 0) {
+    HIPOK(hipMemcpyAsync(S->offs, ho, sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(S->dts, hd, sizeof(double) * ns, hipMemcpyHostToDevice, st));
+  }
+  S->tables_ok = true;
+  return APIC_OK;
+}
+
 template <typename T>
 static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, int64_t *done_tags,
-                               int32_t max_done) {
+                               int32_t *done_status, int32_t max_done) {
   apic_tick tk{};
+  int32_t reported = 0;
+  auto report_done = [&](int64_t tag, apic_status status) {
+    if (reported < max_done) {
+      if (done_tags) done_tags[reported] = tag;
+      if (done_status) done_status[reported] = status;
+    }
+    reported += 1;
+  };
+  // ---- cancelled residents leave first (outputs untouched) -------------
+  {
+    std::vector<ServerReq> keep;
+    for (ServerReq &r : S->resident) {
+      if (r.cancelled) {
+        S->used -= r.footprint;
+        S->tables_ok = false;
+      } else {
+        keep.push_back(r);
+      }
+    }
+    S->resident.swap(keep);
+  }
   // ---- admission (FIFO) -------------------------------------------------
   std::vector<ServerReq> joined;
   int64_t n_new = 0;
@@ -161,47 +235,52 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
     S->queue.pop_front();
   }
   tk.admitted = (int32_t)joined.size();
-  // ---- repack when the resident set changed ----------------------------
-  if (!joined.empty() || !S->tables_ok) {
-    const int src = S->cur, dst = 1 - S->cur;
-    void *sx, *sv, *sC, *sm, *dx, *dv, *dC, *dm;
-    arena_cols(S, src, S->n_res, &sx, &sv, &sC, &sm);
-    arena_cols(S, dst, n_new, &dx, &dv, &dC, &dm);
-    std::vector<CopySeg> segs;
-    int64_t off = 0;
-    auto add = [&](const void *ax, const void *av, const void *aC, const void *am,
-                   const uint16_t *ab, int64_t s_stride, int64_t s_off, int64_t count) {
-      CopySeg c;
-      c.sx = ax, c.sv = av, c.sC = aC, c.sm = am, c.sb = ab;
-      c.dx = dx, c.dv = dv, c.dC = dC, c.dm = dm, c.db = S->body[dst];
-      c.s_stride = s_stride, c.s_off = s_off, c.d_stride = n_new, c.d_off = off;
-      c.count = count, c.start = off;
-      segs.push_back(c);
-      off += count;
-    };
-    for (ServerReq &r : S->resident) {
-      if (r.n > 0) add(sx, sv, sC, sm, S->body[src], S->n_res, r.offset, r.n);
-      r.offset = off - r.n;
-    }
-    for (ServerReq &r : joined) {
-      if (r.n > 0) add(r.x, r.v, r.C, r.m, r.body, r.n, 0, r.n);
-      r.offset = off - r.n;
-      S->resident.push_back(r);
-    }
-    TRY(copy_segs<T>(S, st, segs, 0));
-    S->cur = dst;
-    S->n_res = n_new;
-    // scene offsets and time steps for the position update
+  tk.deferred = (int32_t)S->queue.size();  // waiting for room, a slot or budget
+  if (!joined.empty() || !S->tables_ok) TRY(repack<T>(S, st, joined));
+  // ---- one driver step of every resident request -------------------------
+  // Vbar = V + dt {a, 0} is formed inside the step, so a failed step leaves
+  // the arena untouched.  A request whose particles the device rejects
+  // (non-finite values, a body id beyond its bodies, a stencil node outside
+  // its dense grid) is retired with that status and the step is re-run for
+  // the others.
+  void *x, *v, *C, *m;
+  std::vector<apic_scene> table;
+  std::vector<double> dts;
+  std::vector<int32_t> serr;
+  for (int attempt = 0;; ++attempt) {
     const int ns = (int)S->resident.size();
-    size_t toff = sizeof(CopySeg) * (size_t)(2 * S->max_scenes + 2);
-    int64_t *ho = (int64_t *)((char *)S->stage + toff);
-    double *hd = (double *)((char *)S->stage + toff + sizeof(int64_t) * (S->max_scenes + 1));
-    for (int i = 0; i < ns; ++i) ho[i] = S->resident[i].offset, hd[i] = S->resident[i].dt;
-    if (ns > 0) {
-      HIPOK(hipMemcpyAsync(S->offs, ho, sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
-      HIPOK(hipMemcpyAsync(S->dts, hd, sizeof(double) * ns, hipMemcpyHostToDevice, st));
+    if (ns == 0) break;
+    arena_cols(S, S->cur, S->n_res, &x, &v, &C, &m);
+    table.resize(ns);
+    dts.resize(ns);
+    serr.assign(ns, 0);
+    for (int i = 0; i < ns; ++i) {
+      table[i] = S->resident[i].scene;
+      table[i].offset = S->resident[i].offset;
+      table[i].count = S->resident[i].n;
+      dts[i] = S->resident[i].dt;
     }
-    S->tables_ok = true;
+    const apic_status rc = contact_step_attributed(S->ctx, st, table.data(), ns, S->n_res, x, v,
+                                                   C, m, S->body[S->cur], S->prec, dts.data(),
+                                                   serr.data());
+    if (rc == APIC_OK) break;
+    bool any = false;
+    std::vector<ServerReq> keep;
+    for (int i = 0; i < ns; ++i) {
+      ServerReq &r = S->resident[i];
+      if (serr[i]) {
+        any = true;
+        report_done(r.tag, status_of_error_bits(serr[i]));
+        tk.failed += 1;
+        S->used -= r.footprint;
+      } else {
+        keep.push_back(r);
+      }
+    }
+    if (!any || attempt >= 8) return rc;  // not attributable to a request
+    S->resident.swap(keep);
+    std::vector<ServerReq> none;
+    TRY(repack<T>(S, st, none));
   }
   const int ns = (int)S->resident.size();
   tk.resident = ns;
@@ -213,17 +292,6 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
     if (info) *info = tk;
     return APIC_OK;
   }
-  // ---- one driver step of every resident request -------------------------
-  void *x, *v, *C, *m;
-  arena_cols(S, S->cur, S->n_res, &x, &v, &C, &m);
-  std::vector<apic_scene> table(ns);
-  for (int i = 0; i < ns; ++i) {
-    table[i] = S->resident[i].scene;
-    table[i].offset = S->resident[i].offset;
-    table[i].count = S->resident[i].n;
-  }
-  TRY(apic_contact_step_batched(S->ctx, st, table.data(), ns, S->n_res, x, v, C, m,
-                                S->body[S->cur], S->prec, nullptr));
   hipLaunchKernelGGL(k_advance<T>, dim3(grid_for(S->n_res)), dim3(256), 0, st, (T *)x,
                      (const T *)v, S->n_res, S->offs, S->dts, ns);
   HIPOK(hipGetLastError());
@@ -249,7 +317,7 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
   keep.reserve(S->resident.size());
   for (ServerReq &r : S->resident) {
     if (r.done >= r.steps) {
-      if (done_tags && tk.completed < max_done) done_tags[tk.completed] = r.tag;
+      report_done(r.tag, APIC_OK);
       tk.completed += 1;
       S->used -= r.footprint;
       S->tables_ok = false;
@@ -316,19 +384,36 @@ apic_status apic_server_submit(apic_server *S, int64_t tag, const apic_scene *sc
   r.n = sc.count;
   r.x = x, r.v = v, r.C = C, r.m = m, r.body = body_id;
   r.xo = x_out, r.vo = v_out, r.Co = C_out;
-  r.footprint = apic_scene_footprint(r.n, 0, S->prec);
+  r.footprint = apic_scene_footprint(r.n, &sc.grid, S->prec);
   if (r.n > S->cap || (S->budget > 0 && r.footprint > S->budget)) return APIC_E_BUDGET;
   S->queue.push_back(r);
   return APIC_OK;
 }
 
 apic_status apic_server_tick(apic_server *S, void *stream, apic_tick *info, int64_t *done_tags,
-                             int32_t max_done) {
-  if (!S || (done_tags && max_done < 0)) return APIC_E_INVALID;
+                             int32_t *done_status, int32_t max_done) {
+  if (!S || ((done_tags || done_status) && max_done < 0)) return APIC_E_INVALID;
   if (hipSetDevice(S->ctx->device) != hipSuccess) return APIC_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
-  return S->prec == APIC_FP64 ? server_tick<double>(S, st, info, done_tags, max_done)
-                              : server_tick<float>(S, st, info, done_tags, max_done);
+  if (!done_tags && !done_status) max_done = 0;
+  return S->prec == APIC_FP64
+             ? server_tick<double>(S, st, info, done_tags, done_status, max_done)
+             : server_tick<float>(S, st, info, done_tags, done_status, max_done);
+}
+
+apic_status apic_server_cancel(apic_server *S, int64_t tag) {
+  if (!S) return APIC_E_INVALID;
+  for (auto it = S->queue.begin(); it != S->queue.end(); ++it)
+    if (it->tag == tag) {
+      S->queue.erase(it);
+      return APIC_OK;
+    }
+  for (ServerReq &r : S->resident)
+    if (r.tag == tag && !r.cancelled) {
+      r.cancelled = true;
+      return APIC_OK;
+    }
+  return APIC_E_INVALID;
 }
 
 void apic_server_destroy(apic_server *S) {

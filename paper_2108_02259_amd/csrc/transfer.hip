@@ -84,11 +84,12 @@ __device__ __forceinline__ int fresh_lane() {
 
 // The series state Y of a particle, in two row arrays: values 0..3 (the
 // velocity part and the first affine value) in Yv = Y[n][4], values 4..11 in
-// YC = (Y + 4n)[n][8].  For a particle with a contact normal the rule's W
-// takes all of D's affine part, so Y's affine values are exactly zero.
-// `full` is decided per work item (the same particles in every round of a
-// step; Item::full_y, set where the normals are computed): an item none of
-// whose particles lacks a normal reads and writes Yv only.
+// YC = (Y + 4n)[n][8].  For a particle with a contact normal the Coulomb
+// rule's W takes all of D's affine part, so Y's affine values are exactly
+// zero.  `full` is decided per work item (the same particles in every round
+// of a step; Item::full_y, set where the normals are computed, or the scene's
+// Section 2.3 rule, which keeps the affine change where dv.n <= 0): an item
+// none of whose particles lacks a normal reads and writes Yv only.
 template <typename T>
 __device__ __forceinline__ void load_y(const T *Y, int64_t n, int64_t i0, uint32_t li, bool full,
                                        T v[12]) {
@@ -360,14 +361,24 @@ __device__ __forceinline__ void body_normal(const U *tb, int base, const double 
   }
 }
 
-// Section 2.4: undesirable part of the velocity change d at normal n.
+// Undesirable part w of the velocity change d at normal n, and whether the
+// affine change is undesirable too (*keep_C: 1 or 0).  Section 2.4
+// (Coulomb): w by the friction cone, all of the affine change.  Section 2.3
+// (separate, wave-uniform): the whole change where it pulls the particle
+// away from its surface (d.n > 0), nothing otherwise.
 __device__ __forceinline__ void undesirable(const double d[3], const double n[3], double mu,
-                                            double w[3]) {
+                                            bool separate, double w[3], double *keep_C) {
   const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+  *keep_C = 1.0;
   if (dn > 0.0) {
     w[0] = d[0];
     w[1] = d[1];
     w[2] = d[2];
+    return;
+  }
+  if (separate) {
+    w[0] = w[1] = w[2] = 0.0;
+    *keep_C = 0.0;
     return;
   }
   double dt[3];
@@ -756,7 +767,15 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
     T tt[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) tt[c] = lane_ld(t + c * n + i0, li);
-    if (member && sd.n_iter > 0) {  // wave-uniform
+    if (member && sd.n_iter > 0 && a.given_normals) {  // wave-uniform
+      // the caller's normals, already in sorted order
+      bool no_nrm = false;
+      if (active)
+        no_nrm = lane_ld(nrm + i0, li) == T(0) && lane_ld(nrm + n + i0, li) == T(0) &&
+                 lane_ld(nrm + 2 * n + i0, li) == T(0);
+      const uint64_t any = __ballot(no_nrm);
+      if (lane == 0) items[w0 + wave].full_y = any != 0 ? 1 : 0;
+    } else if (member && sd.n_iter > 0) {  // wave-uniform
       // the body-mass tile in the first component of this wave's P2G tile
       load_tile<T, 1>(tq[wave], (const T *)g.bmass, sg.bslot, 1);
       wave_sync();
@@ -788,8 +807,10 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
       T u[3], E[9];
 #pragma unroll
       for (int q = 0; q < 3; ++q) u[q] = lane_ld(vbar + q * n + i0, li);
+      // PIC (Section 2.1.1): the momentum sum has no affine term
+      const bool pic = (sd.flags & APIC_PIC) != 0;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) E[q] = lane_ld(vbar + (3 + q) * n + i0, li);
+      for (int q = 0; q < 9; ++q) E[q] = pic ? T(0) : lane_ld(vbar + (3 + q) * n + i0, li);
       const T mp = lane_ld(m + i0, li);
       for (int pass = 0; pass < passes; ++pass) {
         if (rank == pass) p2g(tq[wave], base, S, mp, u, E);
@@ -866,14 +887,24 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       T hv[3], hC[9];
       g2p(tile[wave], base, S, T(2) / (h * h), hv, hC);
       const T *vbi = vbar + i0;
-      const bool full = it.full_y != 0;  // some particle of the item has no normal
+      // full series rows: some particle of the item has no normal, or the
+      // Section 2.3 rule may leave a constrained particle's affine change in Y
+      const bool full = it.full_y != 0 || (sd.flags & APIC_RULE_SEPARATE) != 0;
+      // PIC: C is not part of the transferred state; H passes the affine
+      // part through (H Vbar keeps Vbar's C, H W keeps W's zero C), so the
+      // series never moves it.  keepC = 0 zeroes G's affine part.
+      const bool pic = (sd.flags & APIC_PIC) != 0;  // wave-uniform
+      const T keepC = pic ? T(0) : T(1);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) hC[c] *= keepC;
       if (finishing) {
         const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
 #pragma unroll
           for (int c = 0; c < 3; ++c) v_out[c * n + dst] = hv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) C_out[c * n + dst] = hC[c];
+          for (int c = 0; c < 9; ++c)
+            C_out[c * n + dst] = pic ? lane_ld(vbi + (3 + c) * n, li) : hC[c];
         } else {
           T yr[12];
           load_y(Y, n, i0, li, full, yr);
@@ -889,7 +920,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
 #pragma unroll
           for (int c = 0; c < 3; ++c) D[c] = hv[c] - lane_ld(vbi + c * n, li);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - lane_ld(vbi + (3 + c) * n, li);
+          for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - keepC * lane_ld(vbi + (3 + c) * n, li);
         } else {
           T yr[12];
           load_y(Y, n, i0, li, full, yr);
@@ -901,17 +932,17 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
         const T *ni = nrm + i0;
         const double nd[3] = {(double)lane_ld(ni, li), (double)lane_ld(ni + n, li),
                               (double)lane_ld(ni + 2 * n, li)};
-        if (nd[0] == 0.0 && nd[1] == 0.0 && nd[2] == 0.0) {
+        if (nd[0] == 0.0 && nd[1] == 0.0 && nd[2] == 0.0) {  // unconstrained
 #pragma unroll
           for (int c = 0; c < 12; ++c) W[c] = T(0);
         } else {
           const double dd[3] = {(double)D[0], (double)D[1], (double)D[2]};
-          double wv[3];
-          undesirable(dd, nd, sd.mu, wv);
+          double wv[3], kc;
+          undesirable(dd, nd, sd.mu, (sd.flags & APIC_RULE_SEPARATE) != 0, wv, &kc);
 #pragma unroll
           for (int c = 0; c < 3; ++c) W[c] = (T)wv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) W[3 + c] = D[3 + c];
+          for (int c = 0; c < 9; ++c) W[3 + c] = D[3 + c] * (T)kc;
         }
         T yr[12];
 #pragma unroll
@@ -988,14 +1019,18 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
         make_stencil(tt, h, S);
         T hv[3], hC[9];
         g2p(tile[0], particle_base(lane_ld(a.keys + i0, li)), S, T(2) / (h * h), hv, hC);
+        const bool pic = (sd.flags & APIC_PIC) != 0;  // PIC: C passes through (see k_iter)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) hC[c] *= pic ? T(0) : T(1);
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
 #pragma unroll
           for (int c = 0; c < 3; ++c) out[c] = hv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) out[3 + c] = hC[c];
+          for (int c = 0; c < 9; ++c)
+            out[3 + c] = pic ? lane_ld(vbar + (3 + c) * n + i0, li) : hC[c];
         } else {
           T yr[12];
-          load_y(Y, n, i0, li, it.full_y != 0, yr);
+          load_y(Y, n, i0, li, it.full_y != 0 || (sd.flags & APIC_RULE_SEPARATE) != 0, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) out[c] = lane_ld(vbar + c * n + i0, li) + (yr[c] + hv[c]);
 #pragma unroll
@@ -1025,7 +1060,7 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
       for (int d = 0; d < 3; ++d) {
         xp[d] = direct ? lane_ld(x + d * n + i0, li) : x[d * n + dst];
         vv[d] = (double)out[d];
-        r[d] = (double)xp[d] - sd.origin[d];
+        r[d] = (double)xp[d] - sd.x_ref[d];
       }
 #pragma unroll
       for (int c = 0; c < 9; ++c) CC[c] = (double)out[3 + c];

@@ -57,17 +57,34 @@ def test_null_context_is_rejected_before_any_launch():
     assert rc == _lib.E_INVALID
 
 
-def test_footprint_is_monotone():
+def test_footprint_is_monotone_and_bounded_by_a_dense_grid():
     L = _lib.lib()
-    a = L.apic_scene_footprint(1000, 0, _lib.FP32_MIXED)
-    b = L.apic_scene_footprint(100000, 0, _lib.FP32_MIXED)
-    c = L.apic_scene_footprint(100000, 0, _lib.FP64)
+    sparse = _lib.make_grid(1.0)
+    a = L.apic_scene_footprint(1000, ctypes.byref(sparse), _lib.FP32_MIXED)
+    b = L.apic_scene_footprint(100000, ctypes.byref(sparse), _lib.FP32_MIXED)
+    c = L.apic_scene_footprint(100000, ctypes.byref(sparse), _lib.FP64)
     assert 0 < a < b < c
-    assert L.apic_scene_footprint(-1, 0, _lib.FP64) == -1
+    assert L.apic_scene_footprint(100000, None, _lib.FP64) == c
+    dense = _lib.make_grid(1.0, dims=(16, 16, 16))
+    assert L.apic_scene_footprint(100000, ctypes.byref(dense), _lib.FP64) < c
+    assert L.apic_scene_footprint(-1, None, _lib.FP64) == -1
 
 
 def test_scene_table_layout_matches_header():
     # offset, count (16) + grid (24 + 8 + 12 -> 48 with padding) + mu + n_iter + n_bodies
+    # + flags + reserved + accel + x_ref
     assert ctypes.sizeof(_lib.Grid) == 48
-    assert ctypes.sizeof(_lib.Scene) == 16 + 48 + 8 + 8
-    assert ctypes.sizeof(_lib.Report) == 8 * 16 + 8 * 3
+    assert ctypes.sizeof(_lib.Scene) == 16 + 48 + 8 + 8 + 8 + 24 + 24
+    assert ctypes.sizeof(_lib.Report) == 8 * 16 + 8 * 3 + 8
+
+
+def test_invalid_scene_fields_are_rejected_before_any_launch():
+    L = _lib.lib()
+    from paper_2108_02259_amd.contact import scene_table
+    base = dict(offset=0, count=0, h=1.0, n_bodies=1)
+    for bad in (dict(flags=4), dict(accel=(float("nan"), 0, 0)), dict(x_ref=(0, float("inf"), 0)),
+                dict(mu=-1.0), dict(n_iter=-1)):
+        arr = scene_table([dict(base, **bad)])
+        rc = L.apic_contact_step_batched(ctypes.c_void_p(1), None, arr, 1, 0, None, None, None,
+                                         None, None, None, _lib.FP32_MIXED, None)
+        assert rc == _lib.E_INVALID, bad

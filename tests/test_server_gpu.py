@@ -124,7 +124,7 @@ def test_admission_respects_budget_and_slots(ctx):
     from paper_2108_02259_amd._lib import FP32_MIXED, lib
     from paper_2108_02259_amd.contact import Server
     reqs = requests(8, 7, pmin=500, pmax=4000)
-    fps = [lib().apic_scene_footprint(sc.n, 0, FP32_MIXED) for sc, _ in reqs]
+    fps = [lib().apic_scene_footprint(sc.n, None, FP32_MIXED) for sc, _ in reqs]
     budget = int(max(fps) * 1.6)
     srv = Server(ctx, np.float32, max_particles=200_000, max_scenes=3, budget_bytes=budget)
     seen = []
@@ -156,3 +156,101 @@ def test_request_that_never_fits_is_refused(ctx):
         srv.submit(0, table_row(sc), sc.dt, 2, *ins, body, *outs)
     assert e.value.code == E_BUDGET
     srv.close()
+
+
+def test_failing_request_is_retired_and_the_rest_complete(ctx):
+    """A dense-grid request that drifts out of its grid at its second step and
+    a request with a non-finite velocity are retired with their errors; the
+    healthy requests stepped with them complete with their alone results."""
+    import torch
+    from paper_2108_02259_amd._lib import E_INVALID, E_OUT_OF_GRID
+    from paper_2108_02259_amd.contact import Server
+    healthy = requests(11, 3, pmin=400, pmax=1500)
+    alone = {}
+    for tag, r in enumerate(healthy):
+        srv = Server(ctx, np.float32, max_particles=100_000, max_scenes=8)
+        alone[tag] = run(srv, [r], np.float32)[0]
+        srv.close()
+    # leaves its dense grid: fast along +x, the grid ends just past the body
+    out = scenes.random_blobs(12, n_bodies=2, side=4, h=0.5)
+    out.v[:] = 0.0
+    out.v[0] = 40.0
+    origin, dims = scenes.snap_dense_grid(out.x, out.h, halo=3)
+    out.origin, out.dims, out.dt, out.n_iter, out.mu = origin, dims, 0.01, 1, 0.2
+    bad = scenes.random_blobs(13, n_bodies=2, side=4, h=0.5)
+    bad.v[2, 5] = np.nan
+    bad.n_iter, bad.mu, bad.dt = 2, 0.3, 0.01
+    srv = Server(ctx, np.float32, max_particles=100_000, max_scenes=8)
+    held = {}
+    for tag, (sc, steps) in list(enumerate(healthy)) + [(10, (out, 5)), (11, (bad, 3))]:
+        ins, body, outs = tensors(sc, np.float32)
+        srv.submit(tag, table_row(sc), sc.dt, steps, *ins, body, *outs)
+        held[tag] = outs
+    done = set()
+    for _ in range(40):
+        _, fin = srv.tick()
+        done.update(fin)
+        if len(done) == len(healthy) and len(srv.failed) == 2:
+            break
+    say(f"  failed {srv.failed}")
+    assert srv.failed == {10: E_OUT_OF_GRID, 11: E_INVALID}
+    assert done == set(range(len(healthy)))
+    for tag, (sc, _) in enumerate(healthy):
+        xm, vm, Cm = (o.cpu().numpy() for o in held[tag])
+        xa, va, Ca = alone[tag]
+        assert parity_error(vm, Cm, va, Ca, sc.h) <= FP32_TOL
+        assert np.abs(xm - xa).max() <= FP32_TOL * max(1.0, np.abs(xa).max())
+    srv.close()
+    del torch
+
+
+def test_cancel_queued_and_resident_requests(ctx):
+    from paper_2108_02259_amd._lib import ApicError
+    from paper_2108_02259_amd.contact import Server
+    reqs = requests(14, 3, pmin=300, pmax=800)
+    srv = Server(ctx, np.float32, max_particles=100_000, max_scenes=1)
+    held = {}
+    for tag, (sc, _) in enumerate(reqs):
+        ins, body, outs = tensors(sc, np.float32)
+        for o in outs:
+            o.fill_(7.0)
+        srv.submit(tag, table_row(sc), sc.dt, 4, *ins, body, *outs)
+        held[tag] = outs
+    info, _ = srv.tick()               # request 0 resident, 1 and 2 queued
+    assert info["resident"] == 1 and info["deferred"] == 2
+    srv.cancel(2)                      # queued
+    srv.cancel(0)                      # resident: leaves at the next tick
+    with pytest.raises(ApicError):
+        srv.cancel(99)
+    done = set()
+    for _ in range(10):
+        _, fin = srv.tick()
+        done.update(fin)
+    assert done == {1}
+    for tag in (0, 2):
+        assert all(np.all(o.cpu().numpy() == 7.0) for o in held[tag])
+    srv.close()
+
+
+def test_server_acceleration_matches_the_resident_driver(ctx):
+    """A request with a mechanical acceleration follows the resident driver
+    (Vbar = V + dt {a, 0} each step) with the same acceleration."""
+    from paper_2108_02259_amd.contact import Server, Sim
+    sc = scenes.random_blobs(15, n_bodies=2, side=5, h=0.5)
+    sc.mu, sc.n_iter, sc.dt = 0.3, 2, 0.01
+    row = dict(table_row(sc), accel=(0.0, -9.81, 2.0))
+    srv = Server(ctx, np.float64, max_particles=10_000, max_scenes=2)
+    ins, body, outs = tensors(sc, np.float64)
+    srv.submit(0, row, sc.dt, 3, *ins, body, *outs)
+    for _ in range(3):
+        srv.tick()
+    xs, vs, Cs = (o.cpu().numpy() for o in outs)
+    srv.close()
+    ins2, body2, _ = tensors(sc, np.float64)
+    sim = Sim(ctx, [dict(row, offset=0, count=sc.n)], [sc.dt], *ins2, body2)
+    sim.step(3)
+    xg, vg, Cg = (t.cpu().numpy() for t in sim.read())
+    sim.close()
+    assert parity_error(vs, Cs, vg, Cg, sc.h) <= FP64_TOL
+    assert np.abs(xs - xg).max() <= 1e-12 * max(1.0, np.abs(xg).max())
+    assert np.abs(vs - sc.v).max() > 0.05   # the acceleration acted
