@@ -190,6 +190,7 @@ static apic_status plan_tables(apic_ctx *ctx, Workspace &W, Plan &P, const apic_
       d.x_ref[k] = scenes[s].x_ref[k];
     }
     d.flags = scenes[s].flags;
+    if (d.flags) P.variants = true;
     d.offset = scenes[s].offset;
     d.count = scenes[s].count;
     d.n_iter = scenes[s].n_iter;
@@ -441,6 +442,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.item_wg = P.item_wg;
   a.group = P.group;
   a.given_normals = normals != nullptr ? 1 : 0;
+  a.variants = P.variants ? 1 : 0;
   if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
@@ -748,6 +750,9 @@ static void enqueue_plan_step(apic_plan *PL, hipStream_t st, const apic_scene *t
                               const T *x, T *v, T *C, const T *m, const uint16_t *body,
                               const T *normals, apic_report *reports, int32_t *status) {
   Plan &P = PL->plan;
+  // a caller's device table may set flags the plan's own table has not
+  const bool plan_variants = P.variants;
+  if (table) P.variants = true;
   enqueue_prefix<T>(P, st, x, body, nullptr, true, table ? table : PL->abi, PL->sc_plan);
   enqueue_sort<T>(P, st, x, body, nullptr);
   enqueue_body<T>(P, st, x, v, C, m, body, (T *)PL->ws.ptr[kVbar], nullptr, nullptr, (T *)P.ms,
@@ -757,6 +762,7 @@ static void enqueue_plan_step(apic_plan *PL, hipStream_t st, const apic_scene *t
     launch_fill_reports(P.red, P.cnt, P.body_max, P.ns, reports, st);
   }
   if (status) launch_status(P.cnt, status, st);
+  P.variants = plan_variants;
 }
 
 // ---------------------------------------------------------------------------

@@ -92,7 +92,7 @@ struct Plan {
   int32_t *node_count = nullptr;  // bodies with mass per shared node (reports)
   int32_t *body_max = nullptr;    // per scene: most bodies at one node
   int32_t *scene_err = nullptr;   // per scene: error bits of its particles
-  bool given_normals = false;
+  bool variants = false;  // some scene carries flags (or a device table may set them)
   GridPtrs g = {};
 };
 

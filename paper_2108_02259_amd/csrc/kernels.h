@@ -143,6 +143,7 @@ struct StepArgs {
   int xcd_split;         // 1: each XCD walks one contiguous eighth of the items
   int group;             // work items merged per workgroup before the flush (1, 4, 8)
   int given_normals;     // 1: the normals array holds the caller's normals
+  int variants;          // 1: some scene may carry flags (APIC_PIC, APIC_RULE_SEPARATE)
 };
 
 template <typename T>

@@ -361,24 +361,14 @@ __device__ __forceinline__ void body_normal(const U *tb, int base, const double 
   }
 }
 
-// Undesirable part w of the velocity change d at normal n, and whether the
-// affine change is undesirable too (*keep_C: 1 or 0).  Section 2.4
-// (Coulomb): w by the friction cone, all of the affine change.  Section 2.3
-// (separate, wave-uniform): the whole change where it pulls the particle
-// away from its surface (d.n > 0), nothing otherwise.
+// Section 2.4: undesirable part of the velocity change d at normal n.
 __device__ __forceinline__ void undesirable(const double d[3], const double n[3], double mu,
-                                            bool separate, double w[3], double *keep_C) {
+                                            double w[3]) {
   const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
-  *keep_C = 1.0;
   if (dn > 0.0) {
     w[0] = d[0];
     w[1] = d[1];
     w[2] = d[2];
-    return;
-  }
-  if (separate) {
-    w[0] = w[1] = w[2] = 0.0;
-    *keep_C = 0.0;
     return;
   }
   double dt[3];
@@ -839,7 +829,10 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
 // Y is laid out by particle in two row arrays (see load_y).
 // Scenes with n_iter == k-1 finish in round k: they write Vhat and scatter
 // nothing.  Round max n_iter + 1 only finishes (k_final).
-template <typename T, bool FIRST, int G>
+// VAR: scenes may carry flags (PIC transfers, the Section 2.3 rule); without
+// it the flags are ignored and none of their code is compiled in (the batch
+// has none), which keeps the common kernel's register budget.
+template <typename T, bool FIRST, int G, bool VAR>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
 void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *nrm, T *Y,
             GridPtrs g, const uint32_t *perm, T *v_out, T *C_out) {
@@ -889,14 +882,13 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
       const T *vbi = vbar + i0;
       // full series rows: some particle of the item has no normal, or the
       // Section 2.3 rule may leave a constrained particle's affine change in Y
-      const bool full = it.full_y != 0 || (sd.flags & APIC_RULE_SEPARATE) != 0;
+      const int flags = VAR ? sd.flags : 0;  // wave-uniform
+      const bool full = it.full_y != 0 || (flags & APIC_RULE_SEPARATE) != 0;
       // PIC: C is not part of the transferred state; H passes the affine
       // part through (H Vbar keeps Vbar's C, H W keeps W's zero C), so the
       // series never moves it.  keepC = 0 zeroes G's affine part.
-      const bool pic = (sd.flags & APIC_PIC) != 0;  // wave-uniform
-      const T keepC = pic ? T(0) : T(1);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) hC[c] *= keepC;
+      const bool pic = (flags & APIC_PIC) != 0;
+      const T keepC = pic ? T(0) : T(1);  // applied where hC is used
       if (finishing) {
         const int64_t dst = perm ? (int64_t)lane_ld(perm + i0, li) : i0 + li;
         if (FIRST) {  // N = 0: Vhat = H Vbar exactly as gathered
@@ -912,7 +904,7 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 3; ++c) v_out[c * n + dst] = lane_ld(vbi + c * n, li) + (yr[c] + hv[c]);
 #pragma unroll
           for (int c = 0; c < 9; ++c)
-            C_out[c * n + dst] = lane_ld(vbi + (3 + c) * n, li) + (yr[3 + c] + hC[c]);
+            C_out[c * n + dst] = lane_ld(vbi + (3 + c) * n, li) + (yr[3 + c] + keepC * hC[c]);
         }
       } else {
         T D[12];
@@ -920,14 +912,14 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
 #pragma unroll
           for (int c = 0; c < 3; ++c) D[c] = hv[c] - lane_ld(vbi + c * n, li);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) D[3 + c] = hC[c] - keepC * lane_ld(vbi + (3 + c) * n, li);
+          for (int c = 0; c < 9; ++c) D[3 + c] = keepC * (hC[c] - lane_ld(vbi + (3 + c) * n, li));
         } else {
           T yr[12];
           load_y(Y, n, i0, li, full, yr);
 #pragma unroll
           for (int c = 0; c < 3; ++c) D[c] = yr[c] + hv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) D[3 + c] = yr[3 + c] + hC[c];
+          for (int c = 0; c < 9; ++c) D[3 + c] = yr[3 + c] + keepC * hC[c];
         }
         const T *ni = nrm + i0;
         const double nd[3] = {(double)lane_ld(ni, li), (double)lane_ld(ni + n, li),
@@ -937,12 +929,21 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
           for (int c = 0; c < 12; ++c) W[c] = T(0);
         } else {
           const double dd[3] = {(double)D[0], (double)D[1], (double)D[2]};
-          double wv[3], kc;
-          undesirable(dd, nd, sd.mu, (sd.flags & APIC_RULE_SEPARATE) != 0, wv, &kc);
+          double wv[3];
+          undesirable(dd, nd, sd.mu, wv);
 #pragma unroll
           for (int c = 0; c < 3; ++c) W[c] = (T)wv[c];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) W[3 + c] = D[3 + c] * (T)kc;
+          for (int c = 0; c < 9; ++c) W[3 + c] = D[3 + c];
+          if (flags & APIC_RULE_SEPARATE) {
+            // Section 2.3: the whole change (Coulomb's W where d.n > 0, which
+            // is d and all of dC), nothing where the change does not pull the
+            // particle away from its surface
+            const double dn = dd[0] * nd[0] + dd[1] * nd[1] + dd[2] * nd[2];
+            if (!(dn > 0.0))
+#pragma unroll
+              for (int c = 0; c < 12; ++c) W[c] = T(0);
+          }
         }
         T yr[12];
 #pragma unroll
@@ -1123,13 +1124,17 @@ void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nr
 template <typename T>
 void launch_round(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
                   T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, hipStream_t st) {
-#define L_ITER(FIRST_) \
-  APIC_LAUNCH((k_iter<T, FIRST_, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, vbar, \
-              nrm, Y, g, perm, v_out, C_out)
-  if (k == 1)
-    APIC_GROUP_DISPATCH(L_ITER, true);
+#define L_ITER(FIRST_, VAR_) \
+  APIC_LAUNCH((k_iter<T, FIRST_, G_, VAR_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
+              vbar, nrm, Y, g, perm, v_out, C_out)
+  if (k == 1 && a.variants)
+    APIC_GROUP_DISPATCH(L_ITER, true, true);
+  else if (k == 1)
+    APIC_GROUP_DISPATCH(L_ITER, true, false);
+  else if (a.variants)
+    APIC_GROUP_DISPATCH(L_ITER, false, true);
   else
-    APIC_GROUP_DISPATCH(L_ITER, false);
+    APIC_GROUP_DISPATCH(L_ITER, false, false);
 #undef L_ITER
 }
 

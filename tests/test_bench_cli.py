@@ -17,8 +17,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.stdout == ""
 
 
-def test_counter_summary_has_the_fields_the_bench_reads():
-    d = json.load(open(os.path.join(ROOT, "profiles", "round_kernel_counters.json")))
+import pytest
+
+
+@pytest.mark.parametrize("name", ["round_kernel_slab_block_counters.json",
+                                  "round_kernel_batched_1024_counters.json"])
+def test_counter_summary_has_the_fields_the_bench_reads(name):
+    d = json.load(open(os.path.join(ROOT, "profiles", name)))
     for k in ("kernel", "source_hash", "fetch_kib_per_launch", "write_kib_per_launch",
               "fetch_scale", "write_scale", "hbm_bytes_per_launch", "commands"):
         assert k in d
