@@ -223,6 +223,8 @@ def main():
                     help="steps of the slab scene at mu = 0 and mu = 1 (0 = skip)")
     ap.add_argument("--spheres-steps", type=int, default=60,
                     help="steps of the 256-sphere scene (0 = skip)")
+    ap.add_argument("--ramp-steps", type=int, default=200,
+                    help="driver steps of the reduced ramp per friction value (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tune", choices=("cache", "auto", "off"), default="cache",
@@ -472,6 +474,23 @@ def main():
             log(f"spheres n={sp.n}: {out['spheres']['ms_per_step']:.3f} ms/step, "
                 f"{out['spheres']['value']:.3e} particle-steps/s, parity {ps:.2e}, "
                 f"bodies/node {reps_s[0]['max_bodies_per_node']}")
+
+    # ---- the reduced ramp (Section 3.3 without its FE solver): block slide
+    # against the rigid block's analytic slide, FP64 ---------------------
+    if not args.batched_only and args.ramp_steps > 0:
+        from paper_2108_02259_amd import ramp
+        out["ramp"] = {"workload": "6x6x6 block on a fixed heavy 20x10x3 ramp, gravity 10 tilted "
+                                   "30 deg, grid h = particle spacing, N 4, dt 2e-3, rigid-body "
+                                   "projection of the block after every contact step (FP64)",
+                       "steps": args.ramp_steps, "t": args.ramp_steps * 2e-3, "by_mu": {}}
+        for mu in (0.0, 0.2, 0.4, 0.7):
+            _, disp, _ = ramp.run(ctx, mu, args.ramp_steps, trace_every=args.ramp_steps)
+            t_end = args.ramp_steps * 2e-3
+            out["ramp"]["by_mu"][str(mu)] = {"slide": float(disp[0, -1]),
+                                             "analytic": float(ramp.analytic_slide(t_end, mu)),
+                                             "sink": float(disp[2, -1])}
+            log(f"ramp mu={mu}: slide {disp[0, -1]:.4f} (rigid-block analytic "
+                f"{ramp.analytic_slide(t_end, mu):.4f}), sink {disp[2, -1]:.4f}")
 
     # ---- batched form: 1,024 independent two-body scenes in one set of
     # launches per phase, FP32-mixed, graph replay -------------------------
