@@ -134,8 +134,9 @@ apic_status apic_create(apic_ctx **out, int device, size_t hbm_budget_bytes);
 /* Release the context and its workspace (synchronises its device). */
 void apic_destroy(apic_ctx *ctx);
 
-/* Human-readable name of a status code (static storage). */
-const char *apic_status_string(apic_status s);
+/* Human-readable name of a status code (static storage); any int32 value is
+ * accepted, values that are no apic_status give "unknown status". */
+const char *apic_status_string(int32_t status);
 
 /* The contact step S of one scene (Sections 2.1.2-2.4): overwrites v and C
  * with Vhat.  mu >= 0 is the Coulomb coefficient (Section 2.4), n_iter = N

@@ -579,12 +579,18 @@ namespace apic {
 thread_local LaunchTimer *g_launch_timer = nullptr;
 }
 
+// A launch whose events cannot be created runs untimed (null events).
 void Profiler::events(hipEvent_t *start, hipEvent_t *stop) {
   if (free_events.size() < 2)
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
       if (hipEventCreate(&e) == hipSuccess) free_events.push_back(e);
     }
+  if (free_events.size() < 2) {
+    (void)hipGetLastError();
+    *start = *stop = nullptr;
+    return;
+  }
   *start = free_events.back();
   free_events.pop_back();
   *stop = free_events.back();
@@ -861,8 +867,8 @@ void apic_destroy(apic_ctx *ctx) {
   delete ctx;
 }
 
-const char *apic_status_string(apic_status s) {
-  switch (s) {
+const char *apic_status_string(int32_t status) {
+  switch (status) {
     case APIC_OK: return "ok";
     case APIC_E_INVALID: return "invalid argument";
     case APIC_E_NOMEM: return "device allocation failed";
