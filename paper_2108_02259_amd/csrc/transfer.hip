@@ -302,10 +302,15 @@ __device__ __forceinline__ int cell_rank(bool active, uint32_t cell6, int *passe
   const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
   int rank = active ? below : 0;
-  int mx = active ? rank : 0;
+  // one particle per cell (the common case): a single pass, no reduction
+  if (__ballot(rank > 0) == 0) {
+    *passes = act ? 1 : 0;
+    return rank;
+  }
+  int mx = rank;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-  *passes = act ? mx + 1 : 0;
+  *passes = mx + 1;
   return rank;
 }
 
@@ -376,8 +381,11 @@ __device__ __forceinline__ void undesirable(const double d[3], const double n[3]
   for (int a = 0; a < 3; ++a) dt[a] = d[a] - dn * n[a];
   const double tau = sqrt(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
   const double s = fmin(tau, -mu * dn);
+  // w = d_t (1 - s / |d_t|): one division per particle; exactly 0 when the
+  // change lies in the cone (s = |d_t|)
+  const double f = tau > 0.0 ? (tau - s) / tau : 0.0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) w[a] = tau > 0.0 ? dt[a] - s * dt[a] / tau : 0.0;
+  for (int a = 0; a < 3; ++a) w[a] = f * dt[a];
 }
 
 // Tile of NC components from a [slot][comps_in_buf][64] buffer: slots
@@ -461,11 +469,22 @@ __device__ __forceinline__ void zero_tile(T (*tile)[kTileSize]) {
     for (int q = 0; q < NC; ++q) tile[q][i] = T(0);
 }
 
-// The transfer kernels run one 64-lane wavefront per workgroup.  Lanes
-// exchange data only through LDS, whose instructions complete in issue order
-// within a wavefront, so a compiler ordering point replaces the workgroup
-// barrier -- and, unlike a barrier, does not wait for the flush atomics.
+// Ordering within one wavefront: each wave's LDS tile is written and read
+// only by that wave, and a wave's LDS instructions complete in issue order,
+// so a compiler ordering point suffices between a wave's own phases (it does
+// not wait for the flush atomics).  It orders nothing across waves: every
+// exchange between the waves of a workgroup (the grouped flushes and their
+// tables) goes through group_barrier.
 __device__ __forceinline__ void wave_sync() { LDS_ORDER(); }
+
+// Workgroup barrier for LDS data only: the fences are restricted to LDS, so
+// the waves do not wait here for their global atomics (nothing the
+// workgroup reads later depends on them within the kernel).
+__device__ __forceinline__ void group_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ int item_count(const StepArgs &a) {
   return a.cnt->err ? 0 : a.cnt->n_items;
@@ -610,11 +629,11 @@ __device__ __forceinline__ void flush_group(const StepArgs &a, T (*tiles)[NC][kT
       gl.seg[wv] = sgi;
       gl.sbi[wv] = sbi;
     }
-    __syncthreads();
+    group_barrier();
     group_tables<G>(a, gl);
-    __syncthreads();
+    group_barrier();
     group_flush<T, G, NC, ZERO>(tiles, gl, buf, comps_in_buf);
-    __syncthreads();
+    group_barrier();
   }
 }
 
@@ -655,9 +674,9 @@ __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1
     gl.seg[wave] = sgi;
     gl.sbi[wave] = sbi;
   }
-  __syncthreads();
+  group_barrier();
   group_tables<G, true>(a, gl);
-  __syncthreads();
+  group_barrier();
   const int loff = tile_index_block(0, lane);
   for (int J = wave; J < 27; J += G) {
     const uint32_t mask = __builtin_amdgcn_readfirstlane(gl.mask[J]);
@@ -679,7 +698,7 @@ __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1
     if (s >= 0) unsafeAtomicAdd(&mass[(int64_t)s * kNodesPerBlock + lane], sum);
     if (b >= 0) unsafeAtomicAdd(&bmass[(int64_t)b * kNodesPerBlock + lane], sum);
   }
-  __syncthreads();
+  group_barrier();
 }
 
 // ---------------------------------------------------------------------------
