@@ -428,17 +428,18 @@ def main():
             "kernels_us": kus, "plan": info})
 
         # ---- plain FP64 on the same scene -----------------------------------
-        sim64, tuned["float64"] = warmed(sc, np.float64, args.warmup)
-        t64 = timed(sim64, args.fp64_steps, use_graph)
-        _, drift64, _ = sim64.report()
-        p64 = teacher_forced(sim64, sc, np.float64)
-        sim64.close()
-        out["fp64"] = {"value": n * args.fp64_steps / t64, "unit": "particle-steps/s",
-                       "ms_per_step": 1e3 * t64 / args.fp64_steps, "steps": args.fp64_steps,
-                       "max_drift_P": drift64[0][0], "max_drift_L": drift64[0][1],
-                       "parity": p64, "tol": 1e-10}
-        log(f"fp64: {out['fp64']['ms_per_step']:.3f} ms/step, "
-            f"{out['fp64']['value']:.3e} particle-steps/s, parity {p64:.2e}")
+        if args.fp64_steps > 0:
+            sim64, tuned["float64"] = warmed(sc, np.float64, args.warmup)
+            t64 = timed(sim64, args.fp64_steps, use_graph)
+            _, drift64, _ = sim64.report()
+            p64 = teacher_forced(sim64, sc, np.float64)
+            sim64.close()
+            out["fp64"] = {"value": n * args.fp64_steps / t64, "unit": "particle-steps/s",
+                           "ms_per_step": 1e3 * t64 / args.fp64_steps, "steps": args.fp64_steps,
+                           "max_drift_P": drift64[0][0], "max_drift_L": drift64[0][1],
+                           "parity": p64, "tol": 1e-10}
+            log(f"fp64: {out['fp64']['ms_per_step']:.3f} ms/step, "
+                f"{out['fp64']['value']:.3e} particle-steps/s, parity {p64:.2e}")
 
         # ---- the slab scene at mu = 0 and mu = 1 ----------------------------
         if args.mu_steps > 0:

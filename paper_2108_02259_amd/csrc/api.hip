@@ -29,6 +29,12 @@ apic_status Workspace::ensure(int id, size_t bytes) {
     return APIC_OK;
   }
   if (size[id] >= bytes) return APIC_OK;
+  // a growing workspace rounds up by `slack` (within the budget), so that a
+  // slowly growing batch reallocates a logarithmic number of times
+  if (slack > 1.0) {
+    const size_t want = ((size_t)((double)bytes * slack) + 255) & ~(size_t)255;
+    if (!budget || held - size[id] + want <= budget) bytes = want;
+  }
   size_t held_after = held - size[id] + bytes;
   if (budget && held_after > budget) return APIC_E_BUDGET;
   if (ptr[id]) {
@@ -506,34 +512,19 @@ template <typename T>
 static apic_status step_impl(apic_ctx *ctx, Workspace &W, hipStream_t st,
                              const apic_scene *scenes, int32_t ns, int64_t n, const T *x, T *v,
                              T *C, const T *m, const uint16_t *body, apic_report *reports,
-                             const T *normals = nullptr, int32_t *scene_err = nullptr,
-                             const double *dt = nullptr) {
+                             const T *normals = nullptr) {
   Plan P;
-  TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED, dt,
-                  st));
-  if (scene_err) std::fill(scene_err, scene_err + ns, 0);
+  TRY(plan_tables(ctx, W, P, scenes, ns, n, sizeof(T) == 8 ? APIC_FP64 : APIC_FP32_MIXED,
+                  nullptr, st));
   if (n == 0) {
     if (reports)
       for (int s = 0; s < ns; ++s) std::memset(&reports[s], 0, sizeof(apic_report));
     return APIC_OK;
   }
-  // on a device-detected error: the failing scenes' error bits, if asked for
-  auto attribute = [&](apic_status rc) -> apic_status {
-    if (rc != APIC_OK && scene_err && !W.arena) {
-      apic_status r2 = ctx->host_stage(sizeof(int32_t) * ns);
-      if (r2 == APIC_OK && hipMemcpyAsync(ctx->stage, P.scene_err, sizeof(int32_t) * ns,
-                                          hipMemcpyDeviceToHost, st) == hipSuccess &&
-          hipStreamSynchronize(st) == hipSuccess)
-        std::memcpy(scene_err, ctx->stage, sizeof(int32_t) * ns);
-      else
-        (void)hipGetLastError();
-    }
-    return rc;
-  };
   enqueue_prefix<T>(P, st, x, body, nullptr, false);
   Counters c;
   TRY(read_back(ctx, W, &c, P.cnt, sizeof(Counters), st));
-  TRY(attribute(status_from_err(c.err)));
+  TRY(status_from_err(c.err));
   TRY(plan_buffers(ctx, W, P, c.key_blocks, c.smap_total, c.bmap_total, 1.0, st));
   TRY(W.ensure(kVbar, sizeof(T) * 12 * n));
   enqueue_sort<T>(P, st, x, body, nullptr);
@@ -562,7 +553,7 @@ static apic_status step_impl(apic_ctx *ctx, Workspace &W, hipStream_t st,
                          hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
   std::memcpy(&c, stg + rbytes, sizeof(Counters));
-  TRY(attribute(status_from_err(c.err)));
+  TRY(status_from_err(c.err));
   if (c.err) return APIC_E_DEVICE;
   if (reports) {
     std::vector<int32_t> bmax(ns);
@@ -805,22 +796,55 @@ static apic_status scratch_address(int device, void **out) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-apic_status contact_step_attributed(apic_ctx *ctx, void *stream, const apic_scene *scenes,
-                                    int32_t n_scenes, int64_t n_total, const void *x, void *v,
-                                    void *C, const void *m, const uint16_t *body_id,
-                                    apic_precision prec, const double *dt, int32_t *scene_err) {
-  if (!ctx) return APIC_E_INVALID;
+apic_plan *plan_new(apic_ctx *ctx, double slack) {
+  apic_plan *PL = new apic_plan();
+  PL->ctx = ctx;
+  PL->ws.budget = ctx->ws.budget;
+  PL->ws.slack = slack;
+  return PL;
+}
+
+apic_status plan_measure(apic_plan *PL, hipStream_t st, const apic_scene *scenes,
+                         int32_t n_scenes, int64_t n_total, const void *x,
+                         const uint16_t *body_id, apic_precision prec, double headroom,
+                         const double *dt) {
   TRY(validate_scenes(scenes, n_scenes, n_total));
-  if (n_total > 0 && (!x || !v || !C || !m || !body_id)) return APIC_E_INVALID;
-  if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
-  hipStream_t st = (hipStream_t)stream;
+  if (n_total < 1 || !x || !body_id) return APIC_E_INVALID;
+  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
+  if (!(headroom >= 1.0) || !(headroom <= 64.0)) return APIC_E_INVALID;
+  if (dt)
+    for (int32_t s = 0; s < n_scenes; ++s)
+      if (!std::isfinite(dt[s])) return APIC_E_INVALID;
+  apic_ctx *ctx = PL->ctx;
+  PL->plan = Plan{};  // every field is derived again below (buffers are kept)
+  Plan &P = PL->plan;
+  TRY(plan_tables(ctx, PL->ws, P, scenes, n_scenes, n_total, prec, dt, st));
+  const size_t sbytes = sizeof(SceneDev) * n_scenes, abytes = sizeof(apic_scene) * n_scenes;
+  TRY(PL->ws.ensure(kPlanSc, sbytes));
+  TRY(PL->ws.ensure(kPlanAbi, abytes));
+  PL->sc_plan = (SceneDev *)PL->ws.ptr[kPlanSc];
+  PL->abi = (apic_scene *)PL->ws.ptr[kPlanAbi];
+  TRY(ctx->host_stage(abytes));
+  std::memcpy(ctx->stage, scenes, abytes);
+  HIPOK(hipMemcpyAsync(PL->sc_plan, P.sc, sbytes, hipMemcpyDeviceToDevice, st));
+  HIPOK(hipMemcpyAsync(PL->abi, ctx->stage, abytes, hipMemcpyHostToDevice, st));
   if (prec == APIC_FP64)
-    return step_impl<double>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const double *)x,
-                             (double *)v, (double *)C, (const double *)m, body_id, nullptr,
-                             nullptr, scene_err, dt);
-  return step_impl<float>(ctx, ctx->ws, st, scenes, n_scenes, n_total, (const float *)x,
-                          (float *)v, (float *)C, (const float *)m, body_id, nullptr, nullptr,
-                          scene_err, dt);
+    enqueue_prefix<double>(P, st, (const double *)x, body_id, nullptr, false);
+  else
+    enqueue_prefix<float>(P, st, (const float *)x, body_id, nullptr, false);
+  Counters c;
+  TRY(read_back(ctx, PL->ws, &c, P.cnt, sizeof(Counters), st));
+  TRY(status_from_err(c.err));
+  TRY(plan_buffers(ctx, PL->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom, st));
+  TRY(PL->ws.ensure(kVbar, (size_t)P.tbytes * 12 * n_total));
+  HIPOK(hipStreamSynchronize(st));
+  return APIC_OK;
+}
+
+apic_status plan_scene_errors(apic_plan *PL, hipStream_t st, int32_t *out) {
+  const Plan &P = PL->plan;
+  if (!P.scene_err || P.ns < 1) return APIC_E_INVALID;  // no layout has run
+  return read_back(PL->ctx, PL->ws, out, P.scene_err, sizeof(int32_t) * P.ns, st);
 }
 
 apic_status status_of_error_bits(int32_t err) {
@@ -961,46 +985,14 @@ apic_status apic_plan_create(apic_ctx *ctx, void *stream, const apic_scene *scen
                              apic_plan **out) {
   if (!ctx || !out) return APIC_E_INVALID;
   *out = nullptr;
-  TRY(validate_scenes(scenes, n_scenes, n_total));
-  if (n_total < 1 || !x || !body_id) return APIC_E_INVALID;
-  if (prec != APIC_FP64 && prec != APIC_FP32_MIXED) return APIC_E_INVALID;
-  if (!(headroom >= 1.0) || !(headroom <= 64.0)) return APIC_E_INVALID;
   if (hipSetDevice(ctx->device) != hipSuccess) return APIC_E_DEVICE;
-  hipStream_t st = (hipStream_t)stream;
-  apic_plan *PL = new apic_plan();
-  PL->ctx = ctx;
-  PL->ws.budget = ctx->ws.budget;
-  auto fail = [&](apic_status rc) {
+  apic_plan *PL = plan_new(ctx);
+  const apic_status rc = plan_measure(PL, (hipStream_t)stream, scenes, n_scenes, n_total, x,
+                                      body_id, prec, headroom, nullptr);
+  if (rc != APIC_OK) {
     apic_plan_destroy(PL);
     return rc;
-  };
-  Plan &P = PL->plan;
-  apic_status rc = plan_tables(ctx, PL->ws, P, scenes, n_scenes, n_total, prec, nullptr, st);
-  if (rc) return fail(rc);
-  const size_t sbytes = sizeof(SceneDev) * n_scenes, abytes = sizeof(apic_scene) * n_scenes;
-  if ((rc = PL->ws.ensure(kPlanSc, sbytes)) || (rc = PL->ws.ensure(kPlanAbi, abytes)))
-    return fail(rc);
-  PL->sc_plan = (SceneDev *)PL->ws.ptr[kPlanSc];
-  PL->abi = (apic_scene *)PL->ws.ptr[kPlanAbi];
-  if ((rc = ctx->host_stage(abytes))) return fail(rc);
-  std::memcpy(ctx->stage, scenes, abytes);
-  if (hipMemcpyAsync(PL->sc_plan, P.sc, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(PL->abi, ctx->stage, abytes, hipMemcpyHostToDevice, st) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(APIC_E_DEVICE);
   }
-  if (prec == APIC_FP64)
-    enqueue_prefix<double>(P, st, (const double *)x, body_id, nullptr, false);
-  else
-    enqueue_prefix<float>(P, st, (const float *)x, body_id, nullptr, false);
-  Counters c;
-  if ((rc = read_back(ctx, PL->ws, &c, P.cnt, sizeof(Counters), st))) return fail(rc);
-  if ((rc = status_from_err(c.err))) return fail(rc);
-  if ((rc = plan_buffers(ctx, PL->ws, P, c.key_blocks, c.smap_total, c.bmap_total, headroom,
-                         st)))
-    return fail(rc);
-  if ((rc = PL->ws.ensure(kVbar, (size_t)P.tbytes * 12 * n_total))) return fail(rc);
-  if (hipStreamSynchronize(st) != hipSuccess) return fail(APIC_E_DEVICE);
   *out = PL;
   return APIC_OK;
 }

@@ -47,6 +47,7 @@ struct Workspace {
   bool fresh[kNumBufs] = {};  // (re)allocated since the caller last cleared it
   size_t held = 0;
   size_t budget = 0;
+  double slack = 1.0;         // growth factor of a reallocation (>= 1)
   char *arena = nullptr;      // arena mode: the region, its size and the bytes carved
   size_t arena_size = 0;
   apic_status ensure(int id, size_t bytes);
@@ -176,16 +177,21 @@ struct apic_sim {
 
 apic_status validate_scenes(const apic_scene *scenes, int32_t ns, int64_t n_total);
 
-// apic_contact_step_batched with the driver's prediction and error
-// attribution: with dt (host, n_scenes entries, may be null) the step's input
-// is Vbar = V + dt {a, 0} with each scene's accel (formed on the device; v
-// itself is only overwritten by the result); when the device detects an
-// error in some scenes' particles (non-finite values, body id, out of a dense
-// grid), *scene_err (host, n_scenes entries) receives each scene's error
-// bits (apic::kErr*), all zero otherwise.  v and C are untouched on error.
-apic_status contact_step_attributed(apic_ctx *ctx, void *stream, const apic_scene *scenes,
-                                    int32_t n_scenes, int64_t n_total, const void *x, void *v,
-                                    void *C, const void *m, const uint16_t *body_id,
-                                    apic_precision prec, const double *dt, int32_t *scene_err);
 // The apic_status an error word maps to.
 apic_status status_of_error_bits(int32_t err);
+
+// An empty plan on ctx (no buffers yet); filled by plan_measure.  Its
+// buffers grow by `slack` when they grow (a plan re-measured for a growing
+// batch, such as a serving loop's resident set).
+apic_plan *plan_new(apic_ctx *ctx, double slack = 1.0);
+// (Re)measure a batch into PL, reusing its buffers (they only grow):
+// apic_plan_create's work, plus the driver's per-scene drift step dt (host,
+// n_scenes entries, may be null), so that the planned step forms
+// Vbar = V + dt {a, 0} on the device.  Synchronises st once.
+apic_status plan_measure(apic_plan *PL, hipStream_t st, const apic_scene *scenes,
+                         int32_t n_scenes, int64_t n_total, const void *x,
+                         const uint16_t *body_id, apic_precision prec, double headroom,
+                         const double *dt);
+// Each scene's error bits from the plan's last step (host, n_scenes
+// entries); synchronises st.
+apic_status plan_scene_errors(apic_plan *PL, hipStream_t st, int32_t *out);

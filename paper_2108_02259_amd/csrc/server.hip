@@ -4,8 +4,10 @@
 // stride n_res, requests in admission order).  A tick admits queued requests
 // that fit, repacks the arena into its second copy when the resident set has
 // changed (survivors move to their new offsets, newcomers are copied in from
-// the caller's arrays), runs the batched contact step over all residents,
-// advances x, and copies the finished requests out.
+// the caller's arrays), runs the planned contact step over all residents
+// (planned once per resident set; replayed from a graph once the set has
+// settled), advances x, reads the step's status with the tick's one
+// synchronisation, and copies the finished requests out.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -52,10 +54,13 @@ __global__ __launch_bounds__(256) void k_copy_segs(const CopySeg *segs, int nseg
 }
 
 // Driver position update x <- x + dt v (dt of the particle's scene), with
-// the same rounding as the resident driver.
+// the same rounding as the resident driver; skipped when the step that
+// precedes it reported an error in *status.
 template <typename T>
 __global__ __launch_bounds__(256) void k_advance(T *x, const T *v, int64_t n, const int64_t *offs,
-                                                 const double *dt, int ns) {
+                                                 const double *dt, int ns,
+                                                 const int32_t *status) {
+  if (*status != 0) return;  // the step did nothing: neither does the drift
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = ns - 1;
@@ -77,6 +82,14 @@ static unsigned grid_for(int64_t total) {
 }  // namespace apic
 
 using namespace apic;
+
+// Graph capture of the tick's step: after this many ticks of one resident
+// set, and only for sets of at most this many particles.
+constexpr int32_t kStableTicks = 8;
+constexpr int64_t kGraphMaxParticles = 4 << 20;
+// Capacity headroom of a resident set's plan (grown 1.5x on each resize of
+// that set, back to this value for the next set).
+constexpr double kHeadroom = 1.25;
 
 struct ServerReq {
   int64_t tag = 0;
@@ -113,9 +126,31 @@ struct apic_server {
   void *stage = nullptr;
   size_t stage_bytes = 0;
   bool tables_ok = false;
+  // planned step of the current resident set: measured when the set changes,
+  // enqueued without host synchronisation, and once the set has been stepped
+  // unchanged, captured with the drift into a graph that later ticks replay
+  apic_plan *plan = nullptr;
+  bool plan_ok = false;
+  double headroom = kHeadroom;
+  int32_t *status_dev = nullptr;   // the step's apic_status (device)
+  int32_t *status_host = nullptr;  // its copy (pinned)
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t stable = 0;              // ticks stepped with the current plan
 };
 
+// The plan and graph no longer match the resident set.
+static void drop_plan(apic_server *S) {
+  S->plan_ok = false;
+  S->stable = 0;
+  if (S->exec) {
+    (void)hipGraphExecDestroy(S->exec);
+    S->exec = nullptr;
+  }
+}
+
 static size_t tsize(apic_precision p) { return p == APIC_FP64 ? 8 : 4; }
+
 
 // Column pointers of arena copy k at stride n.
 static void arena_cols(apic_server *S, int k, int64_t n, void **x, void **v, void **C, void **m) {
@@ -191,6 +226,8 @@ static apic_status repack(apic_server *S, hipStream_t st, std::vector<ServerReq>
     HIPOK(hipMemcpyAsync(S->dts, hd, sizeof(double) * ns, hipMemcpyHostToDevice, st));
   }
   S->tables_ok = true;
+  drop_plan(S);
+  S->headroom = kHeadroom;
   return APIC_OK;
 }
 
@@ -239,34 +276,20 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
   if (!joined.empty() || !S->tables_ok) TRY(repack<T>(S, st, joined));
   // ---- one driver step of every resident request -------------------------
   // Vbar = V + dt {a, 0} is formed inside the step, so a failed step leaves
-  // the arena untouched.  A request whose particles the device rejects
-  // (non-finite values, a body id beyond its bodies, a stencil node outside
-  // its dense grid) is retired with that status and the step is re-run for
-  // the others.
-  void *x, *v, *C, *m;
+  // the arena untouched (and the drift is skipped on the device).  A request
+  // whose particles the device rejects (non-finite values, a body id beyond
+  // its bodies, a stencil node outside its dense grid) is retired with that
+  // status and the step is re-run for the others; a step that outgrows its
+  // plan is re-planned with more headroom and re-run.
+  void *x = nullptr, *v = nullptr, *C = nullptr, *m = nullptr;
   std::vector<apic_scene> table;
   std::vector<double> dts;
   std::vector<int32_t> serr;
-  for (int attempt = 0;; ++attempt) {
-    const int ns = (int)S->resident.size();
-    if (ns == 0) break;
-    arena_cols(S, S->cur, S->n_res, &x, &v, &C, &m);
-    table.resize(ns);
-    dts.resize(ns);
-    serr.assign(ns, 0);
-    for (int i = 0; i < ns; ++i) {
-      table[i] = S->resident[i].scene;
-      table[i].offset = S->resident[i].offset;
-      table[i].count = S->resident[i].n;
-      dts[i] = S->resident[i].dt;
-    }
-    const apic_status rc = contact_step_attributed(S->ctx, st, table.data(), ns, S->n_res, x, v,
-                                                   C, m, S->body[S->cur], S->prec, dts.data(),
-                                                   serr.data());
-    if (rc == APIC_OK) break;
+  // retire the requests the device flagged; false if none was flagged
+  auto retire_flagged = [&]() -> bool {
     bool any = false;
     std::vector<ServerReq> keep;
-    for (int i = 0; i < ns; ++i) {
+    for (size_t i = 0; i < S->resident.size(); ++i) {
       ServerReq &r = S->resident[i];
       if (serr[i]) {
         any = true;
@@ -277,8 +300,62 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
         keep.push_back(r);
       }
     }
-    if (!any || attempt >= 8) return rc;  // not attributable to a request
-    S->resident.swap(keep);
+    if (any) S->resident.swap(keep);
+    return any;
+  };
+  for (int attempt = 0;; ++attempt) {
+    const int ns = (int)S->resident.size();
+    if (ns == 0 || S->n_res == 0) break;
+    if (attempt >= 16) return APIC_E_DEVICE;
+    arena_cols(S, S->cur, S->n_res, &x, &v, &C, &m);
+    serr.assign(ns, 0);
+    if (!S->plan_ok) {
+      table.resize(ns);
+      dts.resize(ns);
+      for (int i = 0; i < ns; ++i) {
+        table[i] = S->resident[i].scene;
+        table[i].offset = S->resident[i].offset;
+        table[i].count = S->resident[i].n;
+        dts[i] = S->resident[i].dt;
+      }
+      drop_plan(S);
+      if (!S->plan) S->plan = plan_new(S->ctx, 1.5);
+      const apic_status rc = plan_measure(S->plan, st, table.data(), ns, S->n_res, x,
+                                          S->body[S->cur], S->prec, S->headroom, dts.data());
+      if (rc != APIC_OK) {
+        // a particle error found by the layout: name the scenes, retire them
+        if (plan_scene_errors(S->plan, st, serr.data()) != APIC_OK || !retire_flagged())
+          return rc;
+        std::vector<ServerReq> none;
+        TRY(repack<T>(S, st, none));
+        continue;
+      }
+      S->plan_ok = true;
+    }
+    if (S->exec) {
+      HIPOK(hipGraphLaunch(S->exec, st));
+    } else {
+      TRY(apic_plan_step(S->plan, st, nullptr, x, v, C, m, S->body[S->cur], nullptr, nullptr,
+                         S->status_dev));
+      hipLaunchKernelGGL(k_advance<T>, dim3(grid_for(S->n_res)), dim3(256), 0, st, (T *)x,
+                         (const T *)v, S->n_res, S->offs, S->dts, ns, S->status_dev);
+      HIPOK(hipGetLastError());
+    }
+    HIPOK(hipMemcpyAsync(S->status_host, S->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         st));
+    HIPOK(hipStreamSynchronize(st));
+    const apic_status rc = (apic_status)*S->status_host;
+    if (rc == APIC_OK) {
+      S->stable += 1;
+      break;
+    }
+    if (rc == APIC_E_RESIZE) {  // nothing was written: plan again with more room
+      S->headroom = std::min(64.0, S->headroom * 1.5);
+      drop_plan(S);
+      continue;
+    }
+    TRY(plan_scene_errors(S->plan, st, serr.data()));
+    if (!retire_flagged()) return rc;  // not attributable to a request
     std::vector<ServerReq> none;
     TRY(repack<T>(S, st, none));
   }
@@ -292,9 +369,6 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
     if (info) *info = tk;
     return APIC_OK;
   }
-  hipLaunchKernelGGL(k_advance<T>, dim3(grid_for(S->n_res)), dim3(256), 0, st, (T *)x,
-                     (const T *)v, S->n_res, S->offs, S->dts, ns);
-  HIPOK(hipGetLastError());
   // ---- finish: copy out, retire ------------------------------------------
   std::vector<CopySeg> outs;
   int64_t start = 0;
@@ -326,6 +400,28 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
     }
   }
   S->resident.swap(keep);
+  // A small set stepped kStableTicks times with one plan, with nobody
+  // waiting to join, is likely to stay: capture its step and drift for the
+  // next ticks to replay (large sets gain nothing from a graph: their
+  // kernels dwarf the launches).
+  if (S->tables_ok && S->plan_ok && !S->exec && S->stable >= kStableTicks &&
+      S->queue.empty() && !S->resident.empty() && S->n_res > 0 &&
+      S->n_res <= kGraphMaxParticles) {
+    arena_cols(S, S->cur, S->n_res, &x, &v, &C, &m);
+    hipGraph_t g = nullptr;
+    HIPOK(hipStreamBeginCapture(S->capture_stream, hipStreamCaptureModeThreadLocal));
+    const apic_status rc = apic_plan_step(S->plan, S->capture_stream, nullptr, x, v, C, m,
+                                          S->body[S->cur], nullptr, nullptr, S->status_dev);
+    hipLaunchKernelGGL(k_advance<T>, dim3(grid_for(S->n_res)), dim3(256), 0, S->capture_stream,
+                       (T *)x, (const T *)v, S->n_res, S->offs, S->dts,
+                       (int)S->resident.size(), S->status_dev);
+    const hipError_t e = hipStreamEndCapture(S->capture_stream, &g);
+    if (rc != APIC_OK || e != hipSuccess ||
+        hipGraphInstantiate(&S->exec, g, nullptr, nullptr, 0) != hipSuccess)
+      S->exec = nullptr;  // eager steps go on
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+  }
   if (info) *info = tk;
   return APIC_OK;
 }
@@ -356,7 +452,11 @@ apic_status apic_server_create(apic_ctx *ctx, apic_precision prec, int64_t max_p
   ok = ok && hipMalloc((void **)&S->segs, sizeof(CopySeg) * nseg) == hipSuccess &&
        hipMalloc((void **)&S->offs, sizeof(int64_t) * (max_scenes + 1)) == hipSuccess &&
        hipMalloc((void **)&S->dts, sizeof(double) * (max_scenes + 1)) == hipSuccess &&
-       hipHostMalloc(&S->stage, S->stage_bytes, hipHostMallocDefault) == hipSuccess;
+       hipHostMalloc(&S->stage, S->stage_bytes, hipHostMallocDefault) == hipSuccess &&
+       hipMalloc((void **)&S->status_dev, sizeof(int32_t)) == hipSuccess &&
+       hipHostMalloc((void **)&S->status_host, sizeof(int32_t), hipHostMallocDefault) ==
+           hipSuccess &&
+       hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     apic_server_destroy(S);
@@ -420,6 +520,11 @@ void apic_server_destroy(apic_server *S) {
   if (!S) return;
   (void)hipSetDevice(S->ctx->device);
   (void)hipDeviceSynchronize();
+  drop_plan(S);
+  if (S->plan) apic_plan_destroy(S->plan);
+  if (S->status_dev) (void)hipFree(S->status_dev);
+  if (S->status_host) (void)hipHostFree(S->status_host);
+  if (S->capture_stream) (void)hipStreamDestroy(S->capture_stream);
   for (int k = 0; k < 2; ++k) {
     if (S->col[k]) (void)hipFree(S->col[k]);
     if (S->body[k]) (void)hipFree(S->body[k]);
