@@ -299,3 +299,45 @@ def test_lattice_interior_particles_are_unconstrained():
     lone = np.array([[40.5], [40.5], [40.5]])
     _, unc1 = ora.normals(grid(), lone, np.ones(1), np.zeros(1, np.uint16))
     assert unc1[0] == 1
+
+
+# --------------------------------------------------------------------------
+# Mass-gradient normal of a lone particle, in closed form
+# --------------------------------------------------------------------------
+
+def _sum_of_squared_weights():
+    """S(t) = sum_a w_a(t)^2 for the per-axis basis of Appendix B (the three
+    parabolas with 1/4 middle coefficients), and S'(t), as polynomials."""
+    P = np.polynomial.Polynomial
+    t = P([0.0, 1.0])
+    w = [(1 - t) ** 2 / 4, (2 - t ** 2) / 4, (1 + 2 * t - t ** 2) / 4, t ** 2 / 4]
+    S = sum(wa ** 2 for wa in w)
+    return S, S.deriv()
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_lone_particle_normal_closed_form(seed):
+    """A particle alone in its body puts m_i = N_i(x_p) m_p on the grid, so
+    its body-mass gradient at its own position is m_p sum_i N_i grad N_i =
+    (m_p / 2) grad sum_i N_i^2, and with separable weights sum_i N_i^2 =
+    S(t_x) S(t_y) S(t_z).  The outward normal -grad m / |grad m| is therefore
+    along -(S'(t_d) / S(t_d))_d: a dropped derivative term, a wrong sign or
+    a swapped axis in the normals fails this."""
+    rng = np.random.default_rng(seed)
+    S, dS = _sum_of_squared_weights()
+    h = 0.5
+    for _ in range(4):
+        tt = rng.uniform(0.05, 0.95, 3)
+        cell = rng.integers(2, 9, 3)
+        x = ((cell + tt) * h).reshape(3, 1)
+        # a second body far away keeps the scene a contact scene; it shares no node
+        x2 = x + np.array([[40.0], [0.0], [0.0]])
+        xs = np.concatenate([x, x2], 1)
+        v = np.zeros((3, 2))
+        C = np.zeros((9, 2))
+        m = np.array([1.3, 0.7])
+        body = np.array([0, 1], dtype=np.uint16)
+        out = ora.contact_step(grid(h), xs, v, C, m, body, 0.3, 1, want_normals=True)
+        g = np.array([dS(tt[d]) / S(tt[d]) for d in range(3)])
+        expect = -g / np.linalg.norm(g)
+        np.testing.assert_allclose(out["normals"][:, 0], expect, rtol=0, atol=1e-12)
