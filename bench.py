@@ -169,7 +169,7 @@ def serve(ctx, pool, lam, duration, steps, seed, max_particles, max_scenes, budg
     srv = Server(ctx, torch.float32, max_particles, max_scenes, budget)
     step_lat, req_lat, arrive = [], [], {}
     stepped = 0
-    ticks = admitted = deferred_ticks = 0
+    ticks = admitted = deferred_ticks = replayed_ticks = 0
     i = 0
     t0 = time.perf_counter()
     while True:
@@ -186,6 +186,7 @@ def serve(ctx, pool, lam, duration, steps, seed, max_particles, max_scenes, budg
         te = time.perf_counter()
         admitted += info["admitted"]
         deferred_ticks += 1 if info["deferred"] else 0
+        replayed_ticks += info["replayed"]
         if info["resident"] == 0:
             if i < len(t_arr):
                 time.sleep(max(0.0, min(t_arr[i] - (te - t0), duration - (te - t0))))
@@ -204,6 +205,7 @@ def serve(ctx, pool, lam, duration, steps, seed, max_particles, max_scenes, budg
             "admitted": admitted, "completed": len(req_lat), "failed": failed,
             "queued_at_end": int(i) - admitted, "ticks": ticks,
             "ticks_with_requests_deferred": deferred_ticks,
+            "ticks_replaying_a_graph": replayed_ticks,
             "offered_particle_steps_per_s": lam * steps * mean_p,
             "value": stepped / wall, "unit": "particle-steps/s",
             "p50_step_ms": None if not step_lat else 1e3 * percentile(step_lat, 50),
@@ -591,7 +593,8 @@ def main():
             log(f"serving lambda {lam:.0f}/s (offered {r['offered_particle_steps_per_s']:.2e}): "
                 f"{r['value']:.3e} particle-steps/s, step p50 {r['p50_step_ms']:.2f} ms p99 "
                 f"{r['p99_step_ms']:.2f} ms, {r['completed']}/{r['arrived']} done, "
-                f"{r['admitted']} admitted")
+                f"{r['admitted']} admitted, {r['ticks_replaying_a_graph']}/{r['ticks']} ticks "
+                f"replayed a graph")
             serving.append(r)
         # parity of the served step: two pool requests stepped once through a
         # server against the oracle on the same inputs

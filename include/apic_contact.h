@@ -404,6 +404,9 @@ typedef struct {
   int32_t deferred;   /* queued requests held back at admission (no room, slot
                          or budget for the head of the queue) */
   int32_t failed;     /* requests retired by this tick with an error */
+  int32_t replayed;   /* 1 if this tick's step replayed the graph captured for
+                         an unchanged resident set, else 0 */
+  int32_t reserved;
   int64_t particles;  /* particles stepped by this tick */
   int64_t footprint;  /* summed footprint of the requests stepped by this tick */
 } apic_tick;

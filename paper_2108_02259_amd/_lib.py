@@ -65,6 +65,7 @@ class Tick(ctypes.Structure):
     _fields_ = [("resident", ctypes.c_int32), ("admitted", ctypes.c_int32),
                 ("completed", ctypes.c_int32), ("queued", ctypes.c_int32),
                 ("deferred", ctypes.c_int32), ("failed", ctypes.c_int32),
+                ("replayed", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("particles", ctypes.c_int64), ("footprint", ctypes.c_int64)]
 
 

@@ -357,7 +357,7 @@ class Server:
                 self.failed[tag] = st
         info = {"resident": t.resident, "admitted": t.admitted, "completed": t.completed,
                 "queued": t.queued, "deferred": t.deferred, "failed": t.failed,
-                "particles": t.particles, "footprint": t.footprint}
+                "replayed": t.replayed, "particles": t.particles, "footprint": t.footprint}
         return info, done
 
     def cancel(self, tag: int):

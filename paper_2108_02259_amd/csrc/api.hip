@@ -262,12 +262,19 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
                                 int64_t smap_total, int64_t bmap_total, double headroom,
                                 hipStream_t st) {
   const int64_t n = P.n;
-  int64_t kb = std::max<int64_t>(1, (int64_t)std::ceil(key_blocks * headroom));
+  // with headroom (a plan kept while particles move), also an absolute
+  // margin, so that a small scene whose box grows by one block per side
+  // does not outgrow its plan at once
+  const int64_t kmargin = headroom > 1.0 ? 64 : 0, mmargin = headroom > 1.0 ? 512 : 0;
+  int64_t kb = std::max<int64_t>(
+      1, std::max<int64_t>((int64_t)std::ceil(key_blocks * headroom), key_blocks + kmargin));
   int bits = 1;
   while (bits < 32 && ((int64_t)1 << bits) < kb * 64) ++bits;
   P.sort_bits = bits;
-  P.smap_cap = std::max<int64_t>(1, (int64_t)std::ceil(smap_total * headroom));
-  P.bmap_cap = std::max<int64_t>(1, (int64_t)std::ceil(bmap_total * headroom));
+  P.smap_cap = std::max<int64_t>(
+      1, std::max<int64_t>((int64_t)std::ceil(smap_total * headroom), smap_total + mmargin));
+  P.bmap_cap = std::max<int64_t>(
+      1, std::max<int64_t>((int64_t)std::ceil(bmap_total * headroom), bmap_total + mmargin));
   // segments are distinct (body, block) keys present
   P.seg_cap = std::max<int64_t>(1, std::min<int64_t>(n, kb));
   // items: one per segment plus one per 64 particles, plus the run padding

@@ -332,6 +332,7 @@ static apic_status server_tick(apic_server *S, hipStream_t st, apic_tick *info, 
       }
       S->plan_ok = true;
     }
+    tk.replayed = S->exec != nullptr;
     if (S->exec) {
       HIPOK(hipGraphLaunch(S->exec, st));
     } else {

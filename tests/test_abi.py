@@ -76,6 +76,38 @@ def test_scene_table_layout_matches_header():
     assert ctypes.sizeof(_lib.Grid) == 48
     assert ctypes.sizeof(_lib.Scene) == 16 + 48 + 8 + 8 + 8 + 24 + 24
     assert ctypes.sizeof(_lib.Report) == 8 * 16 + 8 * 3 + 8
+    assert ctypes.sizeof(_lib.Tick) == 8 * 4 + 8 * 2
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """Every field offset and struct size of the binding equals what a C
+    compiler makes of include/apic_contact.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"apic_grid": _lib.Grid, "apic_report": _lib.Report, "apic_scene": _lib.Scene,
+               "apic_tuning": _lib.Tuning, "apic_tick": _lib.Tick}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "apic_contact.h"',
+             "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
 
 
 def test_invalid_scene_fields_are_rejected_before_any_launch():

@@ -254,3 +254,44 @@ def test_server_acceleration_matches_the_resident_driver(ctx):
     assert parity_error(vs, Cs, vg, Cg, sc.h) <= FP64_TOL
     assert np.abs(xs - xg).max() <= 1e-12 * max(1.0, np.abs(xg).max())
     assert np.abs(vs - sc.v).max() > 0.05   # the acceleration acted
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, FP64_TOL), (np.float32, FP32_TOL)],
+                         ids=["fp64", "fp32"])
+def test_replayed_ticks_match_the_resident_driver(ctx, dtype, tol):
+    """A resident set that stays unchanged is captured into a graph after a
+    few ticks and replayed: two requests of 24 steps each follow the resident
+    driver stepping the same two scenes, and some of their ticks report a
+    replayed graph."""
+    from paper_2108_02259_amd.contact import Server, Sim
+    scs = [scenes.random_blobs(61, n_bodies=2, side=5, h=0.5),
+           scenes.random_blobs(62, n_bodies=3, side=4, h=0.5)]
+    for i, sc in enumerate(scs):
+        sc.mu, sc.n_iter, sc.dt = 0.2 + 0.2 * i, 1 + i, 0.01
+    steps = 24
+    srv = Server(ctx, dtype, max_particles=20_000, max_scenes=4)
+    held = []
+    for tag, sc in enumerate(scs):
+        ins, body, outs = tensors(sc, dtype)
+        srv.submit(tag, dict(table_row(sc), accel=(0.0, 0.0, -1.0)), sc.dt, steps, *ins, body,
+                   *outs)
+        held.append(outs)
+    replayed = 0
+    for _ in range(steps):
+        info, _ = srv.tick()
+        replayed += info["replayed"]
+    srv.close()
+    say(f"  {replayed} of {steps} ticks replayed a graph")
+    assert replayed >= steps // 4
+    for tag, sc in enumerate(scs):
+        ins2, body2, _ = tensors(sc, dtype)
+        row = dict(table_row(sc), accel=(0.0, 0.0, -1.0), offset=0, count=sc.n)
+        sim = Sim(ctx, [row], [sc.dt], *ins2, body2)
+        sim.step(steps)
+        xg, vg, Cg = (t.cpu().numpy() for t in sim.read())
+        sim.close()
+        xs, vs, Cs = (o.cpu().numpy() for o in held[tag])
+        err = parity_error(vs, Cs, vg, Cg, sc.h)
+        ex = np.abs(xs - xg).max() / max(1.0, np.abs(xg).max())
+        say(f"  request {tag}: v/C {err:.2e} x {ex:.2e}")
+        assert err <= tol and ex <= tol
