@@ -156,13 +156,18 @@ def check_report_sums(rep, x, v, C, m, vg, Cg, h, origin=(0.0, 0.0, 0.0)):
     assert rep["L_scale"] == pytest.approx(before["L_scale"], rel=1e-12)
 
 
-def test_dense_grid_two_cubes_fp64(ctx):
-    """Two cubes head-on (dense grid, mu = 0, 3 iterations), FP64."""
-    say("two cubes dense fp64")
+@pytest.mark.parametrize("dtype,tol", [(np.float64, FP64_TOL), (np.float32, FP32_TOL)],
+                         ids=["fp64", "fp32"])
+def test_dense_grid_two_cubes(ctx, dtype, tol):
+    """Two cubes head-on (dense grid, mu = 0, 3 iterations)."""
+    say("two cubes dense", dtype.__name__)
     sc = scenes.two_cubes()
-    ref = oracle_step(sc, sc.x, sc.v, sc.C, sc.m, sc.mu, sc.n_iter, sc.origin, sc.dims)
-    vg, Cg, _ = gpu_step(ctx, sc, sc.x, sc.v, sc.C, sc.m, sc.mu, sc.n_iter, sc.origin, sc.dims)
-    assert parity_error(vg, Cg, ref["v"], ref["C"], sc.h) <= FP64_TOL
+    x, v, C, m = cast_inputs(sc, dtype)
+    ref = oracle_step(sc, x, v, C, m, sc.mu, sc.n_iter, sc.origin, sc.dims)
+    vg, Cg, _ = gpu_step(ctx, sc, x, v, C, m, sc.mu, sc.n_iter, sc.origin, sc.dims)
+    err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
+    say(f"  parity error {err:.3e}")
+    assert err <= tol
 
 
 def test_out_of_dense_grid_is_reported_and_leaves_inputs(ctx):
@@ -257,6 +262,25 @@ def test_full_size_slab_block(ctx, dtype, tol, mu):
     err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
     say(f"  parity error {err:.3e}, blocks {rep['grid_blocks']}")
     assert err <= tol
+    check_report_sums(rep, x, v, C, m, vg, Cg, sc.h)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, FP32_TOL), (np.float64, FP64_TOL)],
+                         ids=["fp32", "fp64"])
+def test_full_size_spheres(ctx, dtype, tol):
+    """The 256-sphere scene (539,904 particles, 256 bodies, mu 0.4, 6
+    iterations): every particle compared with the oracle, the reported sums
+    with host sums, and the most bodies at one node as the bodies' grids
+    overlap."""
+    say("full spheres", dtype.__name__)
+    sc = scenes.spheres()
+    x, v, C, m = cast_inputs(sc, dtype)
+    vg, Cg, rep = gpu_step(ctx, sc, x, v, C, m, sc.mu, sc.n_iter)
+    ref = oracle_step(sc, x, v, C, m, sc.mu, sc.n_iter)
+    err = parity_error(vg, Cg, ref["v"], ref["C"], sc.h)
+    say(f"  n={sc.n} parity error {err:.3e}, bodies per node {rep['max_bodies_per_node']}")
+    assert err <= tol
+    assert rep["max_bodies_per_node"] >= 2
     check_report_sums(rep, x, v, C, m, vg, Cg, sc.h)
 
 
