@@ -94,6 +94,19 @@ def traffic_from_profiles(kernel: str, name: str = "round_kernel_slab_block_coun
     return d.get("hbm_bytes_per_launch")
 
 
+def kernel_traffic_from_profiles(name: str = "round_kernel_slab_block_counters.json"):
+    """Counter bytes per launch of every transfer kernel of the counted run
+    (kernel name -> bytes), if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return {}
+    return {k: v["hbm_bytes_per_launch"] for k, v in d.get("per_kernel", {}).items()}
+
+
 def sq_counters_from_profiles(kernel: str, name: str = "slab_block_sq_counters.json"):
     """VALU/LDS/L2 utilisation of `kernel` from the committed SQ counter runs,
     if they were taken on the current kernel source."""
@@ -387,17 +400,27 @@ def main():
         round_us = kus["round"]
         achieved_tf = n * ROUND_FLOPS_PER_PARTICLE / (round_us * 1e-6) / 1e12
         hbm_kernels = {}
+        group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
+        round_kernel = f"apic::k_iter<float, false, {group}, false>"
+        names = {"round": round_kernel, "mass": f"apic::k_mass<float, {group}>",
+                 "p2g0": f"apic::k_p2g0<float, {group}>", "final": "apic::k_final<float, false>"}
+        counted = kernel_traffic_from_profiles()
         for k, key in (("round", "round"), ("mass", "mass"), ("p2g0", "p2g0"),
                        ("final", "final")):
             per_p, per_node = KERNEL_BYTES[k]["fp32"]
             alg = n * per_p + nodes * per_node
             us = kus[key]
             gbs = alg / (us * 1e-6) / 1e9
-            hbm_kernels[k] = {"kernel_us": us, "alg_bytes_per_launch": alg, "achieved_gbs": gbs,
-                              "frac": gbs / HBM_PEAK_GBS}
-            log(f"  {k:6s} {us:7.1f} us  {gbs:7.0f} GB/s  {100 * gbs / HBM_PEAK_GBS:5.1f} % HBM")
-        group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
-        round_kernel = f"apic::k_iter<float, false, {group}, false>"
+            hbm_kernels[k] = {"kernel": names[k], "kernel_us": us, "alg_bytes_per_launch": alg,
+                              "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            line = f"  {k:6s} {us:7.1f} us  {gbs:7.0f} GB/s  {100 * gbs / HBM_PEAK_GBS:5.1f} % HBM"
+            if names[k] in counted:  # measured bytes (rocprofv3 FETCH + WRITE, calibrated)
+                cb = counted[names[k]]
+                cg = cb / (us * 1e-6) / 1e9
+                hbm_kernels[k].update({"counter_bytes_per_launch": cb, "counter_gbs": cg,
+                                       "counter_frac": cg / HBM_PEAK_GBS})
+                line += f"   counters {cb / 1e6:6.1f} MB {100 * cg / HBM_PEAK_GBS:5.1f} % HBM"
+            log(line)
         out.update({
             "value": value, "ms_per_step": ms_per_step,
             "config": {"workload": "slab_block: 64x64x16 block moving at (2,0,-0.5) 0.5h above "
