@@ -18,6 +18,13 @@
  *
  * Every floating-point quantity is double; accumulation runs in particle-index
  * order so the result is deterministic.
+ *
+ * Pins: every function is checked against closed forms, special cases,
+ * brute force or library routines by the CPU tests (oracle pins and
+ * variants).  Parity unpinned: the driver's multi-step trajectories beyond a
+ * few steps, and the body-mass-gradient normal of several particles at
+ * general positions (pinned only for flat faces, symmetric cases and a lone
+ * particle, and through the full-step pins).
  */
 #include <math.h>
 #include <stdint.h>
