@@ -400,10 +400,12 @@ def main():
         round_us = kus["round"]
         achieved_tf = n * ROUND_FLOPS_PER_PARTICLE / (round_us * 1e-6) / 1e12
         hbm_kernels = {}
-        group = (tuned.get("float32") or {}).get("best", {}).get("p2g_group", 4)
-        round_kernel = f"apic::k_iter<float, false, {group}, false>"
-        names = {"round": round_kernel, "mass": f"apic::k_mass<float, {group}>",
-                 "p2g0": f"apic::k_p2g0<float, {group}>", "final": "apic::k_final<float, false>"}
+        best32 = (tuned.get("float32") or {}).get("best", {})
+        group, pairs = best32.get("p2g_group", 4), "true" if best32.get("p2g_pairs") else "false"
+        round_kernel = f"apic::k_iter<float, false, {group}, false, {pairs}>"
+        names = {"round": round_kernel, "mass": f"apic::k_mass<float, {group}, {pairs}>",
+                 "p2g0": f"apic::k_p2g0<float, {group}, {pairs}>",
+                 "final": "apic::k_final<float, false>"}
         counted = kernel_traffic_from_profiles()
         for k, key in (("round", "round"), ("mass", "mass"), ("p2g0", "p2g0"),
                        ("final", "final")):
@@ -572,7 +574,9 @@ def main():
             simb2.step(2)
             ktb = simb2.kernel_times()
             simb2.close()
-            rk = f"apic::k_iter<float, false, {(btune or {}).get('best', {}).get('p2g_group', 1)}, false>"
+            bbest = (btune or {}).get("best", {})
+            rk = (f"apic::k_iter<float, false, {bbest.get('p2g_group', 1)}, false, "
+                  f"{'true' if bbest.get('p2g_pairs') else 'false'}>")
             r_ms, r_cnt = ktb["round"]
             us = 1e3 * r_ms / max(r_cnt, 1)
             alg = nb * ROUND_BYTES_PER_PARTICLE["fp32"] + binfo["shared_blocks"] * 64 * ROUND_BYTES_PER_NODE["fp32"]

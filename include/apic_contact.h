@@ -353,6 +353,13 @@ typedef struct {
   int32_t p2g_group;         /* 1, 4 or 8 work items of one super block per
                                 workgroup, their LDS tiles summed before the
                                 flush to the grid (FP64 uses at most 4) */
+  int32_t p2g_pairs;         /* 1: paired scatter -- in work items whose cells
+                                hold several particles, consecutive lanes of
+                                one cell are paired and one lane of each pair
+                                adds both particles' terms to the LDS tile,
+                                halving the passes over the stencil; 0: one
+                                pass per particle rank in its cell.  FP32-mixed
+                                kernels only (the FP64 path ignores it) */
 } apic_tuning;
 
 /* Read or set the tuning a context uses for `prec` and the size bucket of n

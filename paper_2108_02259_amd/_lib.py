@@ -58,7 +58,8 @@ class Scene(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("item_waves_per_cu", ctypes.c_int32), ("node_wg_per_cu", ctypes.c_int32),
-                ("xcd_split", ctypes.c_int32), ("p2g_group", ctypes.c_int32)]
+                ("xcd_split", ctypes.c_int32), ("p2g_group", ctypes.c_int32),
+                ("p2g_pairs", ctypes.c_int32)]
 
 
 class Tick(ctypes.Structure):
@@ -174,11 +175,12 @@ def report_dict(r: Report) -> dict:
 
 def tuning_dict(t: Tuning) -> dict:
     return {"item_waves_per_cu": t.item_waves_per_cu, "node_wg_per_cu": t.node_wg_per_cu,
-            "xcd_split": t.xcd_split, "p2g_group": t.p2g_group}
+            "xcd_split": t.xcd_split, "p2g_group": t.p2g_group, "p2g_pairs": t.p2g_pairs}
 
 
 def make_tuning(d: dict) -> Tuning:
     t = Tuning()
     for k in ("item_waves_per_cu", "node_wg_per_cu", "xcd_split", "p2g_group"):
         setattr(t, k, int(d[k]))
+    t.p2g_pairs = int(d.get("p2g_pairs", 0))  # absent from tunings recorded before the knob
     return t

@@ -93,13 +93,15 @@ static apic_tuning default_tuning() {
   t.node_wg_per_cu = 8;
   t.xcd_split = 0;
   t.p2g_group = 4;
+  t.p2g_pairs = 0;
   return t;
 }
 
 static bool tuning_ok(const apic_tuning &t) {
   return t.item_waves_per_cu >= 1 && t.item_waves_per_cu <= 64 && t.node_wg_per_cu >= 1 &&
          t.node_wg_per_cu <= 64 && (t.xcd_split == 0 || t.xcd_split == 1) &&
-         (t.p2g_group == 1 || t.p2g_group == 4 || t.p2g_group == 8);
+         (t.p2g_group == 1 || t.p2g_group == 4 || t.p2g_group == 8) &&
+         (t.p2g_pairs == 0 || t.p2g_pairs == 1);
 }
 
 apic_tuning apic_ctx::tuning_for(apic_precision prec, int64_t n) const {
@@ -301,6 +303,7 @@ static apic_status plan_buffers(apic_ctx *ctx, Workspace &W, Plan &P, int32_t ke
     P.node_wg = (int)std::max<int64_t>(1, gn);
     P.xcd_split = tu.xcd_split;
     P.group = grp;
+    P.pairs = P.prec == APIC_FP32_MIXED ? tu.p2g_pairs : 0;
   }
   const int64_t ntiles = std::max<int64_t>(sort_tiles(n), 1);
   const size_t T = P.tbytes;
@@ -456,6 +459,7 @@ static void enqueue_body(Plan &P, hipStream_t st, const T *x, const T *v, const 
   a.group = P.group;
   a.given_normals = normals != nullptr ? 1 : 0;
   a.variants = P.variants ? 1 : 0;
+  a.pairs = P.pairs;
   if (prof) prof->end(APIC_KC_SEGMENTS, st), prof->begin(st);
   const T *t = (const T *)P.t;
   T *nrm = (T *)P.nrm, *Y = (T *)P.Y;
@@ -1347,6 +1351,7 @@ apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
         t.item_waves_per_cu = wv;
         t.xcd_split = xs;
         t.p2g_group = grp;
+        t.p2g_pairs = 0;
         double ms = 0;
         rc = score(t, &ms);
         if (rc != APIC_OK) break;
@@ -1369,6 +1374,18 @@ apic_status apic_autotune(apic_ctx *ctx, void *stream, const apic_scene *scenes,
     tried.push_back(t);
     times.push_back(ms);
     if (ms < best_ms) best_ms = ms, bestt = t;
+  }
+  // stage 3: the paired scatter (FP32-mixed kernels) with the best so far
+  if (rc == APIC_OK && prec == APIC_FP32_MIXED) {
+    apic_tuning t = bestt;
+    t.p2g_pairs = 1;
+    double ms = 0;
+    rc = score(t, &ms);
+    if (rc == APIC_OK) {
+      tried.push_back(t);
+      times.push_back(ms);
+      if (ms < best_ms) best_ms = ms, bestt = t;
+    }
   }
   prof.release();
   if (rc != APIC_OK) {

@@ -69,6 +69,7 @@ struct Plan {
   int item_wg = 1;
   int node_wg = 1;
   int xcd_split = 0;
+  int pairs = 0;
   int group = 1;
   bool ready = false;
   SceneDev *sc = nullptr;

@@ -144,6 +144,7 @@ struct StepArgs {
   int group;             // work items merged per workgroup before the flush (1, 4, 8)
   int given_normals;     // 1: the normals array holds the caller's normals
   int variants;          // 1: some scene may carry flags (APIC_PIC, APIC_RULE_SEPARATE)
+  int pairs;             // 1: paired scatter of same-cell particles (FP32 kernels)
 };
 
 template <typename T>

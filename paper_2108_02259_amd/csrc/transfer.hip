@@ -314,6 +314,220 @@ __device__ __forceinline__ int cell_rank(bool active, uint32_t cell6, int *passe
   return rank;
 }
 
+// The value the next lane holds (lane + 1; zero for lane 63), moved by a DPP
+// wavefront shift, which exchanges registers between lanes without the LDS.
+// What a lane outside the current execution mask holds is not defined: the
+// callers select such values away.
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x130, 0xf,
+                                                            0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x130,
+                                                            0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Paired scatter of crowded work items.  Where cells hold several particles,
+// the lanes holding one cell are consecutive (each wave's particles are
+// ordered by cell), and pass r of cell_rank costs a whole read-add-write of
+// the stencil for the few lanes of rank r.  Here each run of consecutive lanes
+// holding one cell is cut into pairs (its lanes 0-1, 2-3, ...): the first lane
+// of a pair, a unit, scatters the sum of both particles' terms, which it
+// receives from the second by lane exchange; an odd run's last lane is a unit
+// of its own.  Units of one cell are ranked as lanes are in cell_rank, and
+// pass r scatters the units of rank r (with their partners taking part in
+// forming the terms), so one pass writes each node at most once per
+// instruction, as before.  `rank` is the pass a lane takes part in (-1: none).
+struct Pairing {
+  int rank;
+  bool unit;     // writes the tile in its pass
+  bool partner;  // the next lane's particle is this unit's pair
+};
+
+__device__ __forceinline__ Pairing pair_lanes(bool active, uint32_t cell6, int *passes) {
+  const int lane = (int)(threadIdx.x & 63);
+  // active lanes are a prefix of the wave, so an active lane's predecessor is active
+  const int prev = __shfl_up((int)cell6, 1, 64);
+  const uint64_t same = __ballot(active && lane > 0 && prev == (int)cell6);
+  Pairing p;
+  if (same == 0) {  // no two consecutive lanes share a cell: every lane is a unit
+    p.unit = active;
+    p.partner = false;
+    p.rank = cell_rank(active, cell6, passes);
+    if (!active) p.rank = -1;
+    return p;
+  }
+  // position in the run of equal cells: distance to the run's first lane
+  const uint64_t heads = __ballot(active && !((same >> lane) & 1ull));
+  const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
+  const uint64_t hb = heads & le;
+  const int start = hb ? 63 - __clzll((unsigned long long)hb) : lane;
+  p.unit = active && ((lane - start) & 1) == 0;
+  p.partner = p.unit && lane < 63 && ((same >> (lane + 1)) & 1ull) != 0;
+  const int urank = cell_rank(p.unit, cell6, passes);
+  const int pair_rank = __shfl_up(urank, 1, 64);  // a second lane joins its unit's pass
+  p.rank = p.unit ? urank : (active ? pair_rank : -1);
+  return p;
+}
+
+// p2g for the lanes of one pass of the paired scatter (see pair_lanes): every
+// taking part lane forms its particle's row terms; a unit adds its partner's
+// (moved from the next lane, zero without a partner) to its own and writes the
+// sum.  The partner's z weights come along once.
+template <typename T>
+__device__ __forceinline__ void p2g_pair(T (*tq)[kTileSize], int base, const Stencil<T> &S, T m,
+                                         const T u[3], const T E[9], bool unit, bool partner) {
+  T wn[4], wdn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const T a = from_next_lane(S.w[2][c]), b = from_next_lane(S.wdx(2, c));
+    wn[c] = partner ? a : T(0);
+    wdn[c] = partner ? b : T(0);
+  }
+  T mu[3], mE[3][3];
+  pin(m);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    mu[q] = m * u[q];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) mE[q][b] = m * E[3 * q + b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    T A[3], Ay[3], Az[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      A[q] = S.w[0][a] * (mu[q] + mE[q][0] * S.dx(0, a));
+      Ay[q] = S.w[0][a] * mE[q][1];
+      Az[q] = S.w[0][a] * mE[q][2];
+      pin(A[q]);
+      pin(Ay[q]);
+      pin(Az[q]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      T P[3], Q[3], Pn[3], Qn[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        P[q] = S.w[1][b] * (A[q] + Ay[q] * S.dx(1, b));
+        Q[q] = S.w[1][b] * Az[q];
+        pin(P[q]);
+        pin(Q[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const T pn = from_next_lane(P[q]), qn = from_next_lane(Q[q]);
+        Pn[q] = partner ? pn : T(0);
+        Qn[q] = partner ? qn : T(0);
+        pin(Pn[q]);
+        pin(Qn[q]);
+      }
+      if (unit) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int idx = base + a + kTileX * b + kTileZStride * c;
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            tq[q][idx] = fma_t(S.w[2][c], P[q],
+                               fma_t(S.wdx(2, c), Q[q],
+                                     fma_t(wn[c], Pn[q], fma_t(wdn[c], Qn[q], tq[q][idx]))));
+          LDS_ORDER();
+        }
+      }
+    }
+  }
+}
+
+// The scatter passes of a work item: with PAIRS the paired scatter, else one
+// pass per cell rank with every lane a unit of its own.
+template <bool PAIRS>
+__device__ __forceinline__ Pairing scatter_lanes(bool active, uint32_t cell6, int *passes) {
+  if constexpr (PAIRS) {
+    return pair_lanes(active, cell6, passes);
+  } else {
+    Pairing p;
+    p.unit = active;
+    p.partner = false;
+    p.rank = cell_rank(active, cell6, passes);
+    return p;
+  }
+}
+
+// One item's scatter passes.  With PAIRS: plain p2g where a pass has no pairs
+// (every pass of an item with one particle per cell), p2g_pair otherwise.
+template <typename T, bool PAIRS>
+__device__ __forceinline__ void p2g_passes(T (*tq)[kTileSize], int base, const Stencil<T> &S,
+                                           T m, const T u[3], const T E[9], const Pairing &pl,
+                                           int passes) {
+  for (int pass = 0; pass < passes; ++pass) {
+    const bool unit = pl.unit && pl.rank == pass;
+    if constexpr (PAIRS) {
+      if (__ballot(unit && pl.partner) != 0) {
+        if (pl.rank == pass) p2g_pair(tq, base, S, m, u, E, unit, pl.partner);
+      } else if (unit) {
+        p2g(tq, base, S, m, u, E);
+      }
+    } else {
+      if (unit) p2g(tq, base, S, m, u, E);
+    }
+    LDS_ORDER();
+  }
+}
+
+// Mass P2G for one pass of the paired scatter (as p2g_pair).
+template <typename T>
+__device__ __forceinline__ void p2g_mass_pair(T *tm, int base, const Stencil<T> &S, T m,
+                                              bool unit, bool partner) {
+  T wn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const T a = from_next_lane(S.w[2][c]);
+    wn[c] = partner ? a : T(0);
+  }
+  pin(m);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      T wab = S.w[0][a] * S.w[1][b] * m;
+      pin(wab);
+      const T nb = from_next_lane(wab);
+      T wabn = partner ? nb : T(0);
+      pin(wabn);
+      if (unit) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int idx = base + a + kTileX * b + kTileZStride * c;
+          tm[idx] = fma_t(wab, S.w[2][c], fma_t(wabn, wn[c], tm[idx]));
+          LDS_ORDER();
+        }
+      }
+    }
+}
+
+template <typename T, bool PAIRS>
+__device__ __forceinline__ void p2g_mass_passes(T *tm, int base, const Stencil<T> &S, T m,
+                                                const Pairing &pl, int passes) {
+  for (int pass = 0; pass < passes; ++pass) {
+    const bool unit = pl.unit && pl.rank == pass;
+    if constexpr (PAIRS) {
+      if (__ballot(unit && pl.partner) != 0) {
+        if (pl.rank == pass) p2g_mass_pair(tm, base, S, m, unit, pl.partner);
+      } else if (unit) {
+        p2g_mass(tm, base, S, m);
+      }
+    } else {
+      if (unit) p2g_mass(tm, base, S, m);
+    }
+    LDS_ORDER();
+  }
+}
+
+
 // Outward normal from the particle's own-body grid mass: n = -grad m^b / |.|;
 // zero when the gradient vanishes (the particle is then unconstrained).
 template <typename U>
@@ -704,7 +918,7 @@ __device__ __forceinline__ void flush_group_mass(const StepArgs &a, T (*tiles)[1
 // ---------------------------------------------------------------------------
 // grid mass and per-body mass
 // ---------------------------------------------------------------------------
-template <typename T, int G>
+template <typename T, int G, bool PAIRS>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
   __shared__ T tm[G][1][kTileSize];  // one item's mass (shared grid and its body's grid)
@@ -725,7 +939,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
     const int64_t i0 = it.start;
     const uint32_t key = lane_ld(a.keys + i0, li);
     int passes;
-    const int rank = cell_rank(active, key & 63u, &passes);
+    const Pairing pl = scatter_lanes<PAIRS>(active, key & 63u, &passes);
     if (active) {
       T tt[3];
 #pragma unroll
@@ -734,10 +948,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
       make_stencil(tt, (T)a.sc[sg.scene].h, S);
       const T mp = lane_ld(m + i0, li);
       const int base = particle_base(key);
-      for (int pass = 0; pass < passes; ++pass) {
-        if (rank == pass) p2g_mass(&tm[wave][0][0], base, S, mp);
-        LDS_ORDER();
-      }
+      p2g_mass_passes<T, PAIRS>(&tm[wave][0][0], base, S, mp, pl, passes);
     }
     flush_group_mass<T, G>(a, tm, gl, member, it.seg, (T *)g.mass, (T *)g.bmass);
   }
@@ -751,7 +962,7 @@ void k_mass(StepArgs a, const T *t, const T *m, GridPtrs g) {
 // tile (FP64) in the space of its P2G tile, computes the normals of its
 // particles, clears that space and then scatters Vbar.  Normals are skipped
 // for scenes without series rounds (unused there).
-template <typename T, int G>
+template <typename T, int G, bool PAIRS>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_P2G_WAVES)))
 void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *items, GridPtrs g) {
   __shared__ T tq[G][3][kTileSize];
@@ -809,7 +1020,7 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
       wave_sync();
     }
     int passes;
-    const int rank = cell_rank(active, key & 63u, &passes);
+    const Pairing pl = scatter_lanes<PAIRS>(active, key & 63u, &passes);
     if (active) {
       Stencil<T> S;
       make_stencil(tt, (T)sd.h, S);
@@ -821,10 +1032,7 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
 #pragma unroll
       for (int q = 0; q < 9; ++q) E[q] = pic ? T(0) : lane_ld(vbar + (3 + q) * n + i0, li);
       const T mp = lane_ld(m + i0, li);
-      for (int pass = 0; pass < passes; ++pass) {
-        if (rank == pass) p2g(tq[wave], base, S, mp, u, E);
-        LDS_ORDER();
-      }
+      p2g_passes<T, PAIRS>(tq[wave], base, S, mp, u, E, pl, passes);
     }
     flush_group<T, G, 3>(a, tq, gl, member, it.seg, (T *)g.buf[0], 3);
   }
@@ -851,7 +1059,7 @@ void k_p2g0(StepArgs a, const T *t, const T *m, const T *vbar, T *nrm, Item *ite
 // VAR: scenes may carry flags (PIC transfers, the Section 2.3 rule); without
 // it the flags are ignored and none of their code is compiled in (the batch
 // has none), which keeps the common kernel's register budget.
-template <typename T, bool FIRST, int G, bool VAR>
+template <typename T, bool FIRST, int G, bool VAR, bool PAIRS>
 __global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(APIC_ROUND_WAVES)))
 void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *nrm, T *Y,
             GridPtrs g, const uint32_t *perm, T *v_out, T *C_out) {
@@ -973,16 +1181,13 @@ void k_iter(StepArgs a, int k, const T *t, const T *m, const T *vbar, const T *n
     if (!finishing) {
       // every lane has gathered: reuse the tile as the scatter target
       int passes = 0;
-      const int rank = cell_rank(active, key & 63u, &passes);
+      const Pairing pl = scatter_lanes<PAIRS>(active, key & 63u, &passes);
       wave_sync();
       if (member) zero_tile<T, 3>(tile[wave]);
       wave_sync();
       if (active) {
         const T mp = lane_ld(m + i0, li);
-        for (int pass = 0; pass < passes; ++pass) {
-          if (rank == pass) p2g(tile[wave], base, S, mp, W, W + 3);
-          LDS_ORDER();
-        }
+        p2g_passes<T, PAIRS>(tile[wave], base, S, mp, W, W + 3, pl, passes);
       }
       flush_group<T, G, 3, false>(a, tile, gl, member, it.seg, gnext, 3);
     }
@@ -1108,19 +1313,33 @@ __global__ __launch_bounds__(64) void k_final(StepArgs a, int k, const T *t, con
   }
 }
 
-// Workgroup shape of the grouped kernels: a.group waves (1, 4 or 8).
-#define APIC_GROUP_DISPATCH(KERNEL_G, ...)          \
+// Workgroup shape of the grouped kernels: a.group waves (1, 4 or 8), and the
+// paired scatter (FP32 only) when a.pairs is set.
+#define APIC_GROUP_DISPATCH_P(KERNEL_G, P, ...)     \
   do {                                              \
     if (a.group >= 8 && sizeof(T) == 4) {          \
       constexpr int G_ = 8;                         \
+      constexpr bool P_ = P;                        \
       KERNEL_G(__VA_ARGS__);                        \
     } else if (a.group >= 4) {                      \
       constexpr int G_ = 4;                         \
+      constexpr bool P_ = P;                        \
       KERNEL_G(__VA_ARGS__);                        \
     } else {                                        \
       constexpr int G_ = 1;                         \
+      constexpr bool P_ = P;                        \
       KERNEL_G(__VA_ARGS__);                        \
     }                                               \
+  } while (0)
+#define APIC_GROUP_DISPATCH(KERNEL_G, ...)                    \
+  do {                                                        \
+    if constexpr (sizeof(T) == 4) {                           \
+      if (a.pairs) {                                          \
+        APIC_GROUP_DISPATCH_P(KERNEL_G, true, __VA_ARGS__);   \
+        break;                                                \
+      }                                                       \
+    }                                                         \
+    APIC_GROUP_DISPATCH_P(KERNEL_G, false, __VA_ARGS__);      \
   } while (0)
 
 // The launch's arguments with the XCD-split schedule (item_loop) on, where
@@ -1133,7 +1352,7 @@ static StepArgs xcd_split_args(const StepArgs &a, int grid) {
 
 template <typename T>
 void launch_mass(const StepArgs &a, const T *t, const T *m, GridPtrs g, hipStream_t st) {
-#define L_MASS() APIC_LAUNCH((k_mass<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, g)
+#define L_MASS() APIC_LAUNCH((k_mass<T, G_, P_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, g)
   APIC_GROUP_DISPATCH(L_MASS);
 #undef L_MASS
 }
@@ -1142,7 +1361,7 @@ template <typename T>
 void launch_p2g0(const StepArgs &a, const T *t, const T *m, const T *vbar, T *nrm, Item *items,
                  GridPtrs g, hipStream_t st) {
 #define L_P2G0() \
-  APIC_LAUNCH((k_p2g0<T, G_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, nrm, \
+  APIC_LAUNCH((k_p2g0<T, G_, P_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, t, m, vbar, nrm, \
               items, g)
   APIC_GROUP_DISPATCH(L_P2G0);
 #undef L_P2G0
@@ -1152,7 +1371,7 @@ template <typename T>
 void launch_round(const StepArgs &a, int k, const T *t, const T *m, const T *vbar, const T *nrm,
                   T *Y, GridPtrs g, const uint32_t *perm, T *v_out, T *C_out, hipStream_t st) {
 #define L_ITER(FIRST_, VAR_) \
-  APIC_LAUNCH((k_iter<T, FIRST_, G_, VAR_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
+  APIC_LAUNCH((k_iter<T, FIRST_, G_, VAR_, P_>), dim3(a.grid_wg), dim3(64 * G_), 0, st, a, k, t, m, \
               vbar, nrm, Y, g, perm, v_out, C_out)
   if (k == 1 && a.variants)
     APIC_GROUP_DISPATCH(L_ITER, true, true);

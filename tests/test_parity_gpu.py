@@ -335,17 +335,21 @@ def test_unconstrained_particles(ctx, dtype, tol, n_iter):
     assert np.abs(Cg[:, unc]).max() > 0.1
 
 
-TUNINGS = [dict(item_waves_per_cu=w, node_wg_per_cu=nw, xcd_split=x, p2g_group=g)
-           for (w, nw, x, g) in ((16, 8, 0, 1), (16, 8, 1, 1), (16, 8, 0, 4), (24, 4, 1, 4),
-                                 (16, 8, 0, 8), (8, 32, 1, 8), (1, 1, 0, 8))]
+TUNINGS = [dict(item_waves_per_cu=w, node_wg_per_cu=nw, xcd_split=x, p2g_group=g, p2g_pairs=p)
+           for (w, nw, x, g, p) in ((16, 8, 0, 1, 0), (16, 8, 1, 1, 0), (16, 8, 0, 4, 0),
+                                    (24, 4, 1, 4, 0), (16, 8, 0, 8, 0), (8, 32, 1, 8, 0),
+                                    (1, 1, 0, 8, 0), (16, 8, 0, 1, 1), (24, 4, 1, 4, 1),
+                                    (8, 32, 1, 8, 1))]
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, FP64_TOL), (np.float32, FP32_TOL)],
                          ids=["fp64", "fp32"])
 def test_every_launch_tuning_matches_oracle(ctx, dtype, tol):
     """Each launch tuning (waves per CU, XCD split, 1/4/8 work items merged per
-    workgroup) gives the oracle's result; crowded and sparse cell blocks mix
-    so that runs of many items and single-item runs both occur."""
+    workgroup, paired or plain scatter) gives the oracle's result; crowded and
+    sparse cell blocks mix so that runs of many items and single-item runs
+    both occur, and cells hold up to a dozen particles (runs of both parities
+    for the paired scatter)."""
     say("tunings", dtype.__name__)
     sc = scenes.random_blobs(41, n_bodies=3, side=9, h=0.5, spacing_frac=0.45, jitter_frac=0.3)
     x, v, C, m = cast_inputs(sc, dtype)
@@ -364,7 +368,9 @@ def test_set_tuning_rejects_bad_values(ctx):
     from paper_2108_02259_amd._lib import ApicError
     for bad in (dict(item_waves_per_cu=0, node_wg_per_cu=8, xcd_split=0, p2g_group=8),
                 dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=2, p2g_group=8),
-                dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=0, p2g_group=3)):
+                dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=0, p2g_group=3),
+                dict(item_waves_per_cu=16, node_wg_per_cu=8, xcd_split=0, p2g_group=4,
+                     p2g_pairs=2)):
         with pytest.raises(ApicError):
             ctx.set_tuning(np.float32, 1000, bad)
 
@@ -382,6 +388,7 @@ def test_autotune_reads_inputs_only_and_keeps_best(ctx):
     torch.cuda.synchronize()
     assert np.array_equal(vt.cpu().numpy(), v) and np.array_equal(Ct.cpu().numpy(), C)
     assert len(tried) >= 20 and all(ms > 0 for _, ms in tried)
+    assert any(t["p2g_pairs"] == 1 for t, _ in tried)  # the FP32 paired-scatter candidate
     times = [ms for _, ms in tried]
     assert tried[int(np.argmin(times))][0] == best
     assert ctx.get_tuning(np.float32, sc.n) == best
