@@ -21,8 +21,10 @@
  *
  * Pins: every function is checked against closed forms, special cases,
  * brute force or library routines by the CPU tests (oracle pins and
- * variants).  Parity unpinned: the driver's multi-step trajectories beyond a
- * few steps, and the body-mass-gradient normal of several particles at
+ * variants).  Multi-step driving is pinned by invariants (exact translation,
+ * and mirror symmetry, P and L of a symmetric collision at every step).
+ * Parity unpinned: the driver's multi-step trajectories in general, and the
+ * body-mass-gradient normal of several particles at
  * general positions (pinned only for flat faces, symmetric cases and a lone
  * particle, and through the full-step pins).
  */

@@ -58,12 +58,21 @@ def sampled(scs, rng, k_small=4, k_mid=2, mid_cap=30000, k_large=2, large_min=10
             + list(rng.choice(large, size=k_large, replace=False)))
 
 
-def test_full_batch_sampled_scenes_match_oracle_and_alone(ctx):
-    say("building 1,024-scene batch")
+@pytest.mark.parametrize("pairs", [0, 1], ids=["plain", "paired"])
+def test_full_batch_sampled_scenes_match_oracle_and_alone(ctx, pairs):
+    """The full batch in the launch shape the benchmark uses for it (one
+    wave per workgroup, 40 waves per CU), with the plain and the paired
+    scatter: sampled scenes against the oracle and against themselves run
+    alone."""
+    say("building 1,024-scene batch", "paired" if pairs else "plain")
     scs = scenes.batch_scenes()
     ntot = sum(sc.n for sc in scs)
     say(f"  {len(scs)} scenes, {ntot} particles")
     assert len(scs) == 1024 and ntot > 3e7
+    tuning = dict(item_waves_per_cu=40, node_wg_per_cu=16, xcd_split=0, p2g_group=1,
+                  p2g_pairs=pairs)
+    for bucket in range(8, 27):
+        ctx.set_tuning(np.float32, 1 << bucket, tuning)
     sim, table = sim_of(ctx, scs, np.float32)
     sim.step(1, graph=True)
     xg, vg, Cg = (t.cpu().numpy() for t in sim.read())
@@ -89,6 +98,9 @@ def test_full_batch_sampled_scenes_match_oracle_and_alone(ctx):
         assert err <= FP32_TOL and ex <= FP32_TOL and ea <= FP32_TOL
         assert np.abs(xg[:, sl] - xa).max() <= FP32_TOL * max(1.0, np.abs(xa).max())
     say(f"  max drift P {max(d[0] for d in drift):.2e} L {max(d[1] for d in drift):.2e}")
+    default = dict(item_waves_per_cu=32, node_wg_per_cu=8, xcd_split=0, p2g_group=4)
+    for bucket in range(8, 27):
+        ctx.set_tuning(np.float32, 1 << bucket, default)
 
 
 def test_batch_fp64_alone_vs_mix_over_steps(ctx):

@@ -414,6 +414,87 @@ def test_mirror_symmetric_collision():
 
 
 # --------------------------------------------------------------------------
+# P11b Multi-step trajectories (contact step, then x += dt v, repeated)
+# --------------------------------------------------------------------------
+
+def drive(grid, x, v, C, m, body, mu, n_iter, dt, steps, each=None):
+    """The explicit driver the paper's step sits in, reduced to the contact
+    step and the position update (no body forces)."""
+    for k in range(steps):
+        out = ora.contact_step(grid, x, v, C, m, body, mu, n_iter)
+        v, C = out["v"], out["C"]
+        x = x + dt * v
+        if each is not None:
+            each(k, x, v, C)
+    return x, v, C
+
+
+def test_multistep_translation_is_exact():
+    """Two bodies translating apart share no grid node: a uniform velocity is
+    an affine field, which the step reproduces, and it stays uniform as the
+    bodies move, so after k steps v is unchanged and x = x0 + k dt v."""
+    a = scenes.random_blobs(90, n_bodies=1, side=4, h=1.0, random_fields=False)
+    b = scenes.random_blobs(91, n_bodies=1, side=4, h=1.0, random_fields=False)
+    a.v[:] = np.array([[-0.7], [0.2], [0.1]])
+    b.v[:] = np.array([[0.9], [-0.3], [0.4]])
+    b.x[0] += 8.0
+    b.body[:] = 1
+    x0 = np.concatenate([a.x, b.x], 1)
+    v0 = np.concatenate([a.v, b.v], 1)
+    m = np.concatenate([a.m, b.m])
+    body = np.concatenate([a.body, b.body])
+    dt, steps = 0.25, 40
+    x, v, C = drive(quad_grid(h=1.0), x0, v0, np.zeros((9, x0.shape[1])), m, body, 0.4, 3,
+                    dt, steps)
+    np.testing.assert_allclose(v, v0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(C, 0.0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(x, x0 + steps * dt * v0, rtol=0, atol=1e-11)
+
+
+def test_multistep_symmetric_collision_keeps_its_invariants():
+    """A mirror-symmetric head-on collision driven over many steps: every step
+    keeps the mirror symmetry of x, v and C, the total linear momentum and the
+    total angular momentum with the affine spin term (the position update
+    x += dt v leaves m x × v unchanged since v × v = 0), while the bodies do
+    interact."""
+    h, plane = 1.0, 10.0
+    a = scenes.random_blobs(92, n_bodies=1, side=4, h=h, random_fields=True)
+    a.x[0] += plane - a.x[0].max() - 0.3
+    a.v[0] += 1.5                        # towards the mirror plane
+    R = np.diag([-1.0, 1.0, 1.0])
+
+    def mirror_C(Cs):
+        return np.stack([(R @ Cs[:, p].reshape(3, 3) @ R).ravel() for p in range(Cs.shape[1])], 1)
+
+    xb = a.x.copy()
+    xb[0] = 2 * plane - a.x[0]
+    x = np.concatenate([a.x, xb], 1)
+    v = np.concatenate([a.v, R @ a.v], 1)
+    C = np.concatenate([a.C, mirror_C(a.C)], 1)
+    m = np.concatenate([a.m, a.m])
+    body = np.concatenate([np.zeros(a.n, np.uint16), np.ones(a.n, np.uint16)])
+    mom0 = ora.momentum(x, v, C, m, h)
+    n = a.n
+    moved = []
+
+    def check(k, xk, vk, Ck):
+        scale = np.abs(vk).max()
+        xm = xk[:, :n].copy()
+        xm[0] = 2 * plane - xm[0]
+        np.testing.assert_allclose(xk[:, n:], xm, rtol=0, atol=1e-11 * plane)
+        np.testing.assert_allclose(vk[:, n:], R @ vk[:, :n], rtol=0, atol=1e-11 * scale)
+        np.testing.assert_allclose(Ck[:, n:], mirror_C(Ck[:, :n]), rtol=0,
+                                   atol=1e-11 * scale / h)
+        mom = ora.momentum(xk, vk, Ck, m, h)
+        assert np.abs(mom["P"] - mom0["P"]).max() <= 1e-12 * mom0["P_scale"]
+        assert np.abs(mom["L"] - mom0["L"]).max() <= 1e-12 * mom0["L_scale"]
+        moved.append(np.abs(vk[0, :n] - v[0, :n]).max())
+
+    drive(quad_grid(h=h), x, v, C, m, body, 0.3, 3, 0.1, 25, check)
+    assert max(moved) > 0.1             # the contact changed the approach velocity
+
+
+# --------------------------------------------------------------------------
 # P12  Coulomb stick/slip threshold of a block on a plane
 # --------------------------------------------------------------------------
 
