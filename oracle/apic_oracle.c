@@ -23,10 +23,7 @@
  * brute force or library routines by the CPU tests (oracle pins and
  * variants).  Multi-step driving is pinned by invariants (exact translation,
  * and mirror symmetry, P and L of a symmetric collision at every step).
- * Parity unpinned: the driver's multi-step trajectories in general, and the
- * body-mass-gradient normal of several particles at
- * general positions (pinned only for flat faces, symmetric cases and a lone
- * particle, and through the full-step pins).
+ * Parity unpinned: the driver's multi-step trajectories in general.
  */
 #include <math.h>
 #include <stdint.h>

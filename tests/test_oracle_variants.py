@@ -341,3 +341,57 @@ def test_lone_particle_normal_closed_form(seed):
         g = np.array([dS(tt[d]) / S(tt[d]) for d in range(3)])
         expect = -g / np.linalg.norm(g)
         np.testing.assert_allclose(out["normals"][:, 0], expect, rtol=0, atol=1e-12)
+
+
+def _bspline_basis():
+    """The Appendix B basis as scipy's quadratic cardinal B-spline averaged
+    over shifts of +-1/2 (pinned equal to the oracle's basis elsewhere), and
+    its derivative, as functions of u = xi - j."""
+    from scipy.interpolate import BSpline
+    beta = BSpline.basis_element([-1.5, -0.5, 0.5, 1.5], extrapolate=False)
+    dbeta = beta.derivative()
+
+    def ev(f, u):
+        val = f(u)
+        return np.where(np.isnan(val), 0.0, val)
+
+    def phi(u):
+        return 0.5 * (ev(beta, u + 0.5) + ev(beta, u - 0.5))
+
+    def dphi(u):
+        return 0.5 * (ev(dbeta, u + 0.5) + ev(dbeta, u - 0.5))
+
+    return phi, dphi
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_normals_of_many_particles_by_brute_force(seed):
+    """Mass-gradient normals of every particle of a crowded two-body scene at
+    general positions, against a dense brute-force evaluation of their
+    definition: body masses m_j = sum_q N_j(x_q) m_q on every node of the
+    bounding box, then -sum_j m_j grad N_j(x_p), normalised, with the basis
+    taken from scipy's B-splines rather than the oracle's parabolas."""
+    phi, dphi = _bspline_basis()
+    h = 0.5
+    sc = scenes.random_blobs(60 + seed, n_bodies=2, side=3, h=h, jitter_frac=0.3,
+                             spacing_frac=0.8, gap_frac=0.4)
+    xi = sc.x / h                                        # grid units, origin 0
+    lo = np.floor(xi.min(1)).astype(int) - 2
+    hi = np.floor(xi.max(1)).astype(int) + 3
+    axes = [np.arange(lo[d], hi[d] + 1) for d in range(3)]
+    expect = np.zeros((3, sc.n))
+    for b in range(sc.n_bodies):
+        own = sc.body == b
+        # per-axis basis values of the body's particles at every node: [particle, node]
+        w = [phi(xi[d, own][:, None] - axes[d][None, :]) for d in range(3)]
+        mb = np.einsum("p,pi,pj,pk->ijk", sc.m[own], w[0], w[1], w[2])
+        wp = [phi(xi[d, own][:, None] - axes[d][None, :]) for d in range(3)]
+        dw = [dphi(xi[d, own][:, None] - axes[d][None, :]) / h for d in range(3)]
+        g = np.stack([
+            np.einsum("ijk,pi,pj,pk->p", mb, dw[0], wp[1], wp[2]),
+            np.einsum("ijk,pi,pj,pk->p", mb, wp[0], dw[1], wp[2]),
+            np.einsum("ijk,pi,pj,pk->p", mb, wp[0], wp[1], dw[2])])
+        expect[:, own] = -g / np.linalg.norm(g, axis=0)
+    nrm, unc = ora.normals(grid(h), sc.x, sc.m, sc.body)
+    assert not unc.any()
+    np.testing.assert_allclose(nrm, expect, rtol=0, atol=1e-12)
