@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import platform
@@ -74,10 +75,17 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the transfer and layout kernel sources with comments and blank
+    lines removed, so that counters taken on a kernel stay valid while only
+    its comments change."""
     h = hashlib.sha256()
     for f in ("transfer.hip", "layout.hip", "apic_internal.h"):
-        with open(os.path.join(ROOT, "paper_2108_02259_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2108_02259_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -332,16 +332,19 @@ __device__ __forceinline__ double from_next_lane(double v) {
 }
 
 // Paired scatter of crowded work items.  Where cells hold several particles,
-// the lanes holding one cell are consecutive (each wave's particles are
-// ordered by cell), and pass r of cell_rank costs a whole read-add-write of
-// the stencil for the few lanes of rank r.  Here each run of consecutive lanes
-// holding one cell is cut into pairs (its lanes 0-1, 2-3, ...): the first lane
-// of a pair, a unit, scatters the sum of both particles' terms, which it
-// receives from the second by lane exchange; an odd run's last lane is a unit
-// of its own.  Units of one cell are ranked as lanes are in cell_rank, and
-// pass r scatters the units of rank r (with their partners taking part in
-// forming the terms), so one pass writes each node at most once per
-// instruction, as before.  `rank` is the pass a lane takes part in (-1: none).
+// pass r of cell_rank costs a whole read-add-write of the stencil for the few
+// lanes of rank r.  The layout orders particles by cell within each block run
+// of a 64-particle gather wave, so the lanes holding one cell are mostly
+// consecutive (a block that straddles two gather waves gives its items two
+// ordered runs, and a cell may then appear in both).  Here each run of
+// consecutive lanes holding one cell is cut into pairs (its lanes 0-1, 2-3,
+// ...): the first lane of a pair, a unit, scatters the sum of both particles'
+// terms, which it receives from the second by lane exchange; an odd run's last
+// lane is a unit of its own.  Units of one cell, from any run, are ranked as
+// lanes are in cell_rank, and pass r scatters the units of rank r (with their
+// partners taking part in forming the terms), so one pass writes each node at
+// most once per instruction, as before.  `rank` is the pass a lane takes part
+// in (-1: none).
 struct Pairing {
   int rank;
   bool unit;     // writes the tile in its pass
