@@ -120,3 +120,14 @@ def test_invalid_scene_fields_are_rejected_before_any_launch():
         rc = L.apic_contact_step_batched(ctypes.c_void_p(1), None, arr, 1, 0, None, None, None,
                                          None, None, None, _lib.FP32_MIXED, None)
         assert rc == _lib.E_INVALID, bad
+
+
+def test_tuning_dicts_round_trip_and_default_the_paired_scatter():
+    """Tunings recorded before the paired-scatter field existed (the JSON cache
+    format) read back with it off; a full dict round-trips unchanged."""
+    old = dict(item_waves_per_cu=40, node_wg_per_cu=16, xcd_split=0, p2g_group=1)
+    t = _lib.make_tuning(old)
+    assert t.p2g_pairs == 0
+    assert _lib.tuning_dict(t) == dict(old, p2g_pairs=0)
+    new = dict(old, p2g_pairs=1)
+    assert _lib.tuning_dict(_lib.make_tuning(new)) == new
